@@ -1,0 +1,312 @@
+"""Seeded synthetic inputs shared by the GPU path, its tests and the oracle tests.
+
+This module holds no lattice Boltzmann arithmetic.  It builds, for each workload,
+the initial conserved fields Q = (rho, rho u, E) in lattice units and the lattice
+parameter set, from the physical set-ups the paper evaluates (Sec. 3: Sod and
+Becker shock tubes, compressible Taylor-Green vortex; Table 1 for the numerical
+parameters), and it draws the seeded instance mixes of the batched and served
+workloads.  Both the HIP path and the FP64 oracle start from what is built here.
+
+Units (the paper leaves the mapping implicit).  With cell size dx and
+r = dt/dx (the paper's Courant number, Sec. 2.6), density is unscaled and
+    u_lat = r u,  p_lat = r^2 p,  E_lat = r^2 E,  T_lat = r^2 T,
+    mu_lat = mu r / dx,  kappa_lat = kappa r / dx,
+    E_k(phys) = E_k(lat) / r^2,  eps(phys) = eps(lat) / (r^3 dx).
+The conductivity follows Pr = mu c_p / kappa with c_p = gamma/(gamma-1) (Sec. 2.4).
+
+Parameter dict keys (lattice units): nx, ny, nz, bc (per axis, 0 periodic, 1 zero
+gradient), collision (0 regularized with sensor, 1 BGK), mu_law (0 constant,
+1 Sutherland), gamma, mu_ref, kappa_ref, T_ref, T_S, omega[5], sensor_gain, J_min,
+omega_min, rho_min, p_min, rho_ref, E_ref (the uniform reference state whose
+equilibrium the stored populations are shifted by, Sec. 2.2).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+T_SUTHERLAND = 0.4042  # Listing 1
+PERIODIC, ZERO_GRADIENT = 0, 1
+RLB_SENSOR, BGK = 0, 1
+MU_CONSTANT, MU_SUTHERLAND = 0, 1
+
+
+@dataclass
+class Case:
+    name: str
+    params: dict
+    Q0: np.ndarray            # [5, nz, ny, nx] float64, lattice units
+    steps: int
+    diag_every: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def shape(self):
+        return (self.params["nz"], self.params["ny"], self.params["nx"])
+
+    @property
+    def cells(self) -> int:
+        return int(self.params["nx"]) * int(self.params["ny"]) * int(self.params["nz"])
+
+
+def base_params(nx, ny, nz, bc, *, gamma=1.4, mu=0.0, Pr=0.71, mu_law=MU_CONSTANT,
+                T_ref=1.0, omega=1.9, collision=RLB_SENSOR, sensor_gain=20.0, J_min=3e-3,
+                omega_min=1.0, rho_min=1e-4, p_min=1e-4, rho_ref=1.0, E_ref=0.0) -> dict:
+    """Lattice parameter dict; mu and the floors are already in lattice units."""
+    cp = gamma / (gamma - 1.0)
+    om = [float(omega)] * 5 if np.isscalar(omega) else [float(w) for w in omega]
+    return dict(nx=int(nx), ny=int(ny), nz=int(nz), bc=[int(b) for b in bc],
+                collision=int(collision), mu_law=int(mu_law), gamma=float(gamma),
+                mu_ref=float(mu), kappa_ref=float(mu * cp / Pr) if Pr else 0.0,
+                T_ref=float(T_ref), T_S=T_SUTHERLAND, omega=om,
+                sensor_gain=float(sensor_gain), J_min=float(J_min),
+                omega_min=float(omega_min), rho_min=float(rho_min), p_min=float(p_min),
+                rho_ref=float(rho_ref), E_ref=float(E_ref), Pr=float(Pr))
+
+
+def conserved(rho, u, p, gamma):
+    """Primitive -> conserved state of eq. 2 (equation of state only)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    Q = np.empty((5,) + rho.shape)
+    Q[0] = rho
+    for d in range(3):
+        Q[1 + d] = rho * u[d]
+    Q[4] = p / (gamma - 1.0) + 0.5 * rho * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    return Q
+
+
+# --------------------------------------------------------------------------- Sod
+def sod(n=256, ny=4, nz=4, r=0.128, t_end=0.2, left=(1.0, 1.0), right=(0.125, 0.1),
+        gamma=1.4, Pr=0.71, mu=1e-6, omega=1.40, sensor_gain=20.0, J_min=3e-3,
+        omega_min=1.0) -> Case:
+    """Sod shock tube on [0,1] (Sec. 3.2): left/right = (rho, p), u = 0, cell
+    centres x = (i + 1/2)/n, zero gradient at both x ends, periodic in y and z.
+    r = dt/dx is chosen so that the fastest wave (|u| + c <= 2.2) moves at most
+    0.28 cells per step, below the D3Q7 sound speed 1/2; at n = 256, 400 steps
+    reach t = 0.2."""
+    dx = 1.0 / n
+    x = (np.arange(n) + 0.5) * dx
+    rho1 = np.where(x < 0.5, left[0], right[0])
+    p1 = np.where(x < 0.5, left[1], right[1])
+    rho = np.broadcast_to(rho1, (nz, ny, n)).copy()
+    p = np.broadcast_to(p1, (nz, ny, n)).copy() * r * r
+    zero = np.zeros_like(rho)
+    Q = conserved(rho, (zero, zero, zero), p, gamma)
+    prm = base_params(n, ny, nz, (ZERO_GRADIENT, PERIODIC, PERIODIC), gamma=gamma,
+                      mu=mu * r / dx, Pr=Pr, omega=omega, sensor_gain=sensor_gain,
+                      J_min=J_min, omega_min=omega_min, p_min=1e-4 * r * r,
+                      rho_ref=right[0], E_ref=right[1] * r * r / (gamma - 1.0))
+    steps = int(round(t_end / (r * dx)))
+    return Case("sod", prm, Q, steps, 0,
+                dict(dx=dx, r=r, x=x, t_end=steps * r * dx, left=left, right=right, gamma=gamma))
+
+
+# ------------------------------------------------------------ Taylor-Green vortex
+F_MU = {64: 1.8, 128: 0.9, 256: 0.001, 512: 0.01}  # background damping per resolution
+
+
+def f_mu_for(n: int) -> float:
+    """Background damping of the cTGV section; nearest tabulated resolution in log2."""
+    keys = sorted(F_MU)
+    best = min(keys, key=lambda k: abs(math.log2(k) - math.log2(n)))
+    return F_MU[best]
+
+
+def tgv(n=256, mach=1.25, Re=1600.0, Pr=0.71, gamma=1.4, r=0.1, f_mu=None,
+        sensor_gain=40.0, J_min=1e-2, omega_min=1.987, steps=2000, diag_every=50,
+        collision=RLB_SENSOR, dims=None) -> Case:
+    """Compressible Taylor-Green vortex on [0, 2pi)^3 (Sec. 3.3): V0 = rho0 = L0 = 1,
+    u = (sin x cos y cos z, -cos x sin y cos z, 0), pressure of the incompressible
+    solution p = p0 + (1/16)(cos 2x + cos 2y)(cos 2z + 2) with p0 = c0^2/gamma,
+    c0 = 1/M, uniform temperature so rho = p/T0, Sutherland viscosity with
+    mu_ref = 1/Re at T_ref = T0.  Nodes x_i = i dx, dx = 2 pi / n.  The relaxation
+    time follows the background damping rule tau = 1/2 + 4 f_mu nu dt/dx^2."""
+    nx, ny, nz = dims if dims is not None else (n, n, n)
+    dx = 2.0 * math.pi / n
+    c0 = 1.0 / mach
+    p0 = c0 * c0 / gamma
+    T0 = p0
+    x = np.arange(nx) * dx
+    y = np.arange(ny) * dx
+    z = np.arange(nz) * dx
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    ux = np.sin(X) * np.cos(Y) * np.cos(Z)
+    uy = -np.cos(X) * np.sin(Y) * np.cos(Z)
+    uz = np.zeros_like(ux)
+    p = p0 + (1.0 / 16.0) * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+    rho = p / T0
+    Q = conserved(rho, (r * ux, r * uy, r * uz), r * r * p, gamma)
+    mu_lat = (1.0 / Re) * r / dx
+    if f_mu is None:
+        f_mu = f_mu_for(n)
+    tau = 0.5 + 4.0 * f_mu * mu_lat  # nu = mu/rho0 with rho0 = 1
+    omega = 1.0 / tau
+    prm = base_params(nx, ny, nz, (PERIODIC, PERIODIC, PERIODIC), gamma=gamma, mu=mu_lat,
+                      Pr=Pr, mu_law=MU_SUTHERLAND, T_ref=r * r * T0, omega=omega,
+                      collision=collision, sensor_gain=sensor_gain, J_min=J_min,
+                      omega_min=omega_min, p_min=1e-4 * r * r, rho_ref=1.0,
+                      E_ref=r * r * p0 / (gamma - 1.0))
+    return Case("tgv", prm, Q, steps, diag_every,
+                dict(dx=dx, r=r, mach=mach, Re=Re, f_mu=f_mu, tc_per_step=r * dx,
+                     ek_scale=1.0 / (r * r), eps_scale=1.0 / (r ** 3 * dx)))
+
+
+def tgv2d(n=32, u0=0.005, c0=0.05, nu=0.02, Pr=0.71, gamma=1.4, omega=2.0,
+          collision=BGK, nz=1) -> Case:
+    """Two-dimensional low-Mach Taylor-Green vortex, directly in lattice units:
+    u = u0 (sin kx cos ky, -cos kx sin ky, 0), k = 2 pi / n, incompressible pressure
+    p = p0 + rho0 u0^2/4 (cos 2kx + cos 2ky), uniform temperature, constant mu."""
+    k = 2.0 * math.pi / n
+    p0 = c0 * c0 / gamma
+    T0 = p0
+    i = np.arange(n)
+    Z, Y, X = np.meshgrid(np.arange(nz), i, i, indexing="ij")
+    ux = u0 * np.sin(k * X) * np.cos(k * Y)
+    uy = -u0 * np.cos(k * X) * np.sin(k * Y)
+    p = p0 + 0.25 * u0 * u0 * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    rho = p / T0
+    Q = conserved(rho, (ux, uy, np.zeros_like(ux)), p, gamma)
+    prm = base_params(n, n, nz, (PERIODIC, PERIODIC, PERIODIC), gamma=gamma, mu=nu, Pr=Pr,
+                      omega=omega, collision=collision, p_min=1e-12, rho_min=1e-6,
+                      rho_ref=1.0, E_ref=p0 / (gamma - 1.0))
+    return Case("tgv2d", prm, Q, 0, 0, dict(k=k, u0=u0, c0=c0, nu=nu))
+
+
+# ------------------------------------------------------------- Becker viscous shock
+def becker_states(mach, gamma=1.4, rho1=1.0, c1=1.0):
+    """Upstream/downstream states of a normal shock in its own frame."""
+    u1 = mach * c1
+    p1 = rho1 * c1 * c1 / gamma
+    u2 = u1 * ((gamma - 1.0) * mach * mach + 2.0) / ((gamma + 1.0) * mach * mach)
+    m = rho1 * u1
+    cp = gamma / (gamma - 1.0)
+    H = cp * p1 / rho1 + 0.5 * u1 * u1
+    return dict(u1=u1, u2=u2, m=m, H=H, p1=p1, rho1=rho1, cp=cp)
+
+
+def becker_K(mach, mu, gamma=1.4, rho1=1.0, c1=1.0):
+    s = becker_states(mach, gamma, rho1, c1)
+    return 3.0 * s["m"] * (gamma + 1.0) / (8.0 * gamma * mu)
+
+
+def becker_thickness(mach, mu, gamma=1.4, rho1=1.0, c1=1.0):
+    """Maximum-slope thickness (u1 - u2)/max|u'| of the Becker profile."""
+    s = becker_states(mach, gamma, rho1, c1)
+    K = becker_K(mach, mu, gamma, rho1, c1)
+    a, b = math.sqrt(s["u1"]), math.sqrt(s["u2"])
+    return (a + b) / (K * (a - b))
+
+
+def becker_mu_for_thickness(mach, delta, gamma=1.4, rho1=1.0, c1=1.0):
+    s = becker_states(mach, gamma, rho1, c1)
+    a, b = math.sqrt(s["u1"]), math.sqrt(s["u2"])
+    K = (a + b) / (delta * (a - b))
+    return 3.0 * s["m"] * (gamma + 1.0) / (8.0 * gamma * K)
+
+
+def becker_profile(x, mach, mu, x_shock=0.0, gamma=1.4, rho1=1.0, c1=1.0):
+    """Closed-form Becker shock (Pr = 3/4, constant mu, Stokes hypothesis) in its own
+    frame.  With Pr = 3/4 the total enthalpy H = c_p T + u^2/2 is constant, and
+    momentum reduces to (4/3) mu u u' = m (gamma+1)/(2 gamma) (u - u1)(u - u2),
+    whose solution is explicit in x(u):
+        x(u) = [u1 ln((u1-u)/(u1-u2)) - u2 ln((u-u2)/(u1-u2))] / (K (u1-u2)) + C,
+    K = 3 m (gamma+1)/(8 gamma mu).  C places the steepest point u = sqrt(u1 u2) at
+    x_shock.  Inverted by bisection in FP64.  Returns (rho, u, p, T) arrays."""
+    s = becker_states(mach, gamma, rho1, c1)
+    u1, u2, m, H, cp = s["u1"], s["u2"], s["m"], s["H"], s["cp"]
+    K = becker_K(mach, mu, gamma, rho1, c1)
+    d = u1 - u2
+
+    def xof(u):
+        return (u1 * np.log((u1 - u) / d) - u2 * np.log((u - u2) / d)) / (K * d)
+
+    x0 = xof(math.sqrt(u1 * u2))
+    xs = np.asarray(x, dtype=np.float64) - x_shock + x0
+    lo = np.full(xs.shape, u2)   # x(u) decreases with u: x(lo) = +inf
+    hi = np.full(xs.shape, u1)   # x(hi) = -inf
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            xm = xof(mid)
+        go_up = xm > xs          # need larger u to reduce x
+        lo = np.where(go_up, mid, lo)
+        hi = np.where(go_up, hi, mid)
+    u = 0.5 * (lo + hi)
+    rho = m / u
+    T = (H - 0.5 * u * u) / cp
+    p = rho * T
+    return rho, u, p, T
+
+
+def becker(L=1024, mach=2.0, cells_per_front=16.0, ny=4, nz=4, gamma=1.4, omega=1.99,
+           beta_max=4.0, sensor_gain=20.0, J_min=3e-3, omega_min=1.0, u_max=0.05) -> Case:
+    """Stationary Becker shock in lattice units, shock frame, centred in an L-cell tube
+    with zero-gradient ends (Sec. 3.2 configuration, Pr = 3/4, constant mu).
+    The upstream sound speed is set so that |u1| + c1 = u_max; mu is chosen for the
+    requested maximum-slope thickness, capped so that the lattice viscous number
+    beta = 2 nu omega / c_s^2 upstream stays <= beta_max (eq. 6)."""
+    c1 = u_max / (mach + 1.0)
+    mu = becker_mu_for_thickness(mach, cells_per_front, gamma, 1.0, c1)
+    beta = 8.0 * mu * omega
+    if beta > beta_max:
+        mu = beta_max / (8.0 * omega)
+    delta = becker_thickness(mach, mu, gamma, 1.0, c1)
+    x = np.arange(L) + 0.5
+    xs = 0.5 * L
+    rho1d, u1d, p1d, _ = becker_profile(x, mach, mu, xs, gamma, 1.0, c1)
+    rho = np.broadcast_to(rho1d, (nz, ny, L)).copy()
+    ux = np.broadcast_to(u1d, (nz, ny, L)).copy()
+    p = np.broadcast_to(p1d, (nz, ny, L)).copy()
+    zero = np.zeros_like(rho)
+    Q = conserved(rho, (ux, zero, zero), p, gamma)
+    s = becker_states(mach, gamma, 1.0, c1)
+    prm = base_params(L, ny, nz, (ZERO_GRADIENT, PERIODIC, PERIODIC), gamma=gamma, mu=mu,
+                      Pr=0.75, omega=omega, sensor_gain=sensor_gain, J_min=J_min,
+                      omega_min=omega_min, p_min=1e-4 * c1 * c1, rho_ref=1.0,
+                      E_ref=s["p1"] / (gamma - 1.0) + 0.5 * s["u1"] ** 2)
+    return Case("becker", prm, Q, 5000, 0,
+                dict(mach=mach, mu=mu, c1=c1, x_shock=xs, cells_per_front=delta,
+                     gamma=gamma, x=x))
+
+
+def becker_batch(count=64, seed=0, L_range=(512, 8192), mach_range=(1.5, 5.0), **kw):
+    """Seeded mix of Becker instances: tube lengths uniform on L_range (integers),
+    upstream Mach uniform on mach_range."""
+    rng = np.random.default_rng(seed)
+    Ls = rng.integers(L_range[0], L_range[1] + 1, size=count)
+    Ms = rng.uniform(mach_range[0], mach_range[1], size=count)
+    return [becker(int(L), float(M), **kw) for L, M in zip(Ls, Ms)]
+
+
+# ------------------------------------------------------------- random smooth states
+def random_smooth(nx, ny, nz, seed=0, amp=0.05, bc=(PERIODIC, PERIODIC, PERIODIC),
+                  c0=0.08, mach=1.0, collision=RLB_SENSOR, mu=2e-3, omega=1.95,
+                  mu_law=MU_SUTHERLAND, sensor_gain=40.0, J_min=1e-2, omega_min=1.987,
+                  modes=3) -> Case:
+    """Smooth random state for parity tests: a few random Fourier modes on top of a
+    uniform state with sound speed c0 and velocity amplitude mach*c0 (lattice)."""
+    rng = np.random.default_rng(seed)
+    gamma = 1.4
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+
+    def field_():
+        out = np.zeros((nz, ny, nx))
+        for _ in range(modes):
+            k = rng.integers(0, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi)
+            a = rng.standard_normal()
+            out += a * np.cos(2 * math.pi * (k[0] * X / nx + k[1] * Y / ny + k[2] * Z / nz) + ph)
+        return out / modes
+
+    p0 = c0 * c0 / gamma
+    rho = 1.0 + amp * field_()
+    p = p0 * (1.0 + amp * field_())
+    u = [mach * c0 * field_() for _ in range(3)]
+    Q = conserved(rho, u, p, gamma)
+    prm = base_params(nx, ny, nz, bc, gamma=gamma, mu=mu, mu_law=mu_law, T_ref=p0,
+                      omega=omega, collision=collision, sensor_gain=sensor_gain, J_min=J_min,
+                      omega_min=omega_min, p_min=1e-4 * p0, rho_ref=1.0,
+                      E_ref=p0 / (gamma - 1.0))
+    return Case("random", prm, Q, 0, 0, dict(seed=seed))
