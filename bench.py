@@ -1,0 +1,149 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused collide-and-stream update on one MI355X.
+
+Workload: the supersonic compressible Taylor-Green vortex on a 256^3 periodic grid
+in FP32 (Mach 1.25, Re 1600, Pr 0.71, gamma 1.4, Sutherland viscosity, regularized
+collision with the compression sensor), kinetic energy and solenoidal/dilatational
+dissipation reduced every 50 steps.  One "step" is one lattice update of every
+cell.  Inputs are synthetic (the analytic initial field) and resident in HBM
+before the timed region starts.
+
+Prints one JSON line with the metric, a `roofline` object for the collide-and-
+stream kernel (HBM bound: 280 algorithmic bytes per cell update) measured with HIP
+events on the stream the kernel runs on, and a `cpu_baseline` object: the FP64
+oracle timed on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+BYTES_PER_LUP_F32 = 280.0    # 35 populations x 4 B, read and written once
+
+
+def cpu_baseline(target_s=10.0):
+    """The oracle as it stands on a slab of the 256^3 workload (full x-y planes,
+    32 z-planes, periodic), repeated until about target_s of wall time."""
+    import numpy as np
+    import oracle
+    from paper_2609_16361_amd import inputs
+    case = inputs.tgv(n=256, dims=(256, 256, 32))
+    f = oracle.init(case.params, case.Q0)
+    cells = case.cells
+    t0 = time.perf_counter()
+    f, _ = oracle.run(case.params, f, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, int(target_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    f, _ = oracle.run(case.params, f, steps)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(f).all()
+    glups = cells * steps / dt / 1e9
+    return {"value": glups, "unit": "GLUP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, 256x256x32 slab of the 256^3 cTGV initial field, {steps} steps "
+                      f"after 1 warm-up step, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
+    ap.add_argument("--diag-every", type=int, default=50)
+    ap.add_argument("--block", type=int, default=None)
+    ap.add_argument("--nontemporal", type=int, default=None)
+    ap.add_argument("--layout-pad", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bw-probe", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2609_16361_amd import binding, inputs
+
+    binding.load()  # fails loudly if the HIP library has not been built
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    case = inputs.tgv(n=args.n, diag_every=args.diag_every)
+    cells = case.cells
+    solver = binding.Solver(case.params, stream=stream.cuda_stream, block=args.block,
+                            nontemporal=None if args.nontemporal is None else bool(args.nontemporal),
+                            layout_pad=args.layout_pad)
+    solver.init(case.Q0)
+    del case.Q0
+
+    solver.step(args.warmup, args.diag_every)
+    torch.cuda.synchronize()
+    solver.diagnostics()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter()
+    ev0.record(stream)
+    solver.step(args.steps, args.diag_every)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t_host
+    ms = ev0.elapsed_time(ev1)
+
+    recs, status = solver.diagnostics()
+    assert status == binding.LBM_OK and all(r["nonfinite"] == 0 for r in recs), "state diverged"
+    solver.close()
+
+    glups = cells * args.steps / (ms * 1e-3) / 1e9
+    avg_launch_ms = ms / args.steps
+    achieved_gbs = BYTES_PER_LUP_F32 * cells / (avg_launch_ms * 1e-3) / 1e9
+
+    bw = None
+    if not args.no_bw_probe:
+        bw = binding.lbm_bw_probe(2 * 1024 ** 3, 10)
+
+    out = {
+        "metric": "GLUP/s + % HBM roofline (256^3 TGV fp32); batched solves/s, p99 latency",
+        "value": round(glups, 4),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (analytic compressible Taylor-Green initial field)",
+        "config": {"workload": f"compressible Taylor-Green vortex {args.n}^3 periodic FP32, Mach 1.25, "
+                               f"Re 1600, regularized collision + sensor, diagnostics every "
+                               f"{args.diag_every} steps",
+                   "cells": cells, "steps": args.steps, "diag_every": args.diag_every,
+                   "block": args.block or 256, "nontemporal": bool(args.nontemporal),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "bytes_per_lup": BYTES_PER_LUP_F32, "avg_launch_ms": round(avg_launch_ms, 5)},
+        "host_wall_s": round(t_host, 3),
+        "copy_bw_gbs": None if bw is None else round(bw, 1),
+        "diag_records": len(recs),
+        "Ek_last": recs[-1]["Ek"] / cells if recs else None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * grlbm.h -- C ABI of the MI355X (gfx950) five-field gradient-reconstruction
+ * lattice Boltzmann solver for the compressible Navier-Stokes-Fourier equations
+ * (Kummerlaender, Bukreev, Krause).
+ *
+ * What the library computes.  Each call of lbm_step advances the populations of
+ * the five conserved fields Q = (rho, rho u_x, rho u_y, rho u_z, E) (eq. 2) by one
+ * collide-and-stream update per step, exactly as Algorithm 1 lists it: conserved
+ * and first moments, floored primitives, the direct gradient from the
+ * non-equilibrium first moment (eq. 3), the reconstruction operator R of eq. 4
+ * evaluated as the block forward solve of eqs. 5-7, the chain rule to grad u and
+ * grad T, the compression sensor (Sec. 2.5, Listing 2), Newtonian stress and
+ * Fourier flux in the equilibrium flux, a regularized (or BGK) collision, and exact
+ * on-lattice streaming on D3Q7 (c_s^2 = 1/4, 7 populations per field, 35 per cell).
+ *
+ * Units.  Every quantity crossing this ABI is in lattice units: cell size 1, time
+ * step 1.  The solver does not convert units.
+ *
+ * Storage.  One device buffer holds 35 population arrays (structure of arrays,
+ * x fastest), updated in place with the AA access pattern, so a single copy of the
+ * state suffices: 140 bytes per cell in FP32, 70 in FP16.  The stored value is the
+ * deviation f - w_i Q_ref from the equilibrium of a uniform reference state
+ * (Sec. 2.2), Q_ref = (rho_ref, 0, 0, 0, E_ref).
+ *
+ * Threading.  A context is not internally locked: use one context per host thread
+ * at a time.  lbm_last_error is thread-local.
+ *
+ * Errors.  Every call returns an lbm_status; on failure lbm_last_error() describes
+ * it.  No call aborts the process.
+ */
+#ifndef GRLBM_H
+#define GRLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument (message names it)                         */
+  LBM_ENOMEM = -2,     /* device or host allocation failed                            */
+  LBM_EDEVICE = -3,    /* a HIP runtime call failed (message keeps the HIP error)     */
+  LBM_EDIVERGED = -4,  /* a diagnostic reduction saw a non-finite population          */
+  LBM_ESTATE = -5      /* call out of order (e.g. step before init)                    */
+} lbm_status;
+
+typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_ZERO_GRADIENT = 1 } lbm_bc;
+/* Sec. 2.2 / 2.5: the regularized collision with the compression sensor is used
+ * for the shock cases, BGK for smooth ones. */
+typedef enum { LBM_COLL_RLB_SENSOR = 0, LBM_COLL_BGK = 1 } lbm_collision;
+typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1 } lbm_storage;
+/* Listing 1: mu(T) = mu_ref (1+T_S) (T/T_ref)^(3/2) / (T/T_ref + T_S). */
+typedef enum { LBM_MU_CONSTANT = 0, LBM_MU_SUTHERLAND = 1 } lbm_mu_law;
+
+typedef struct {
+  int32_t nx, ny, nz;          /* cells; x is the fastest index of every array        */
+  int32_t bc[3];               /* lbm_bc per axis (x, y, z)                            */
+  int32_t collision;           /* lbm_collision                                        */
+  int32_t storage;             /* lbm_storage of the populations                       */
+  int32_t mu_law;              /* lbm_mu_law                                           */
+  int32_t layout_pad;          /* extra elements between population arrays (>= 0);
+                                  arrays always start on 256-byte boundaries          */
+  double gamma;                /* ratio of specific heats (eq. 2 equation of state)    */
+  double mu_ref, kappa_ref;    /* viscosity and conductivity at T_ref; both scale with
+                                  the same law: mu = mu_ref r(T), kappa = kappa_ref r(T),
+                                  r = 1 (constant) or the Sutherland factor            */
+  double T_ref, T_S;           /* Sutherland reference temperature and constant        */
+  double omega[5];             /* relaxation frequency per field (rho, mx, my, mz, E);
+                                  each in (0, 2]; the three momentum values must be
+                                  equal (the closed-form momentum block needs it)      */
+  double sensor_gain;          /* g of the compression sensor                           */
+  double J_min;                /* dead band of the sensor                               */
+  double omega_min;            /* rate the sensor relaxes towards                       */
+  double rho_min, p_min;       /* positivity floors (Algorithm 1, line 2)               */
+  double rho_ref, E_ref;       /* reference state of the equilibrium shift              */
+} lbm_params;
+
+/* One diagnostic record, reduced over all cells at the start of step `step` (the
+ * state after `step` completed steps): volume sums of the kinetic energy density
+ * rho|u|^2/2, the solenoidal dissipation mu|curl u|^2 and the dilatational
+ * dissipation (4/3) mu (div u)^2 (velocity gradient from the reconstruction), the
+ * totals of the five conserved fields minus N Q_ref, and the number of cells whose
+ * updated populations are not finite. */
+typedef struct {
+  int64_t step;
+  double Ek, eps_s, eps_d;
+  double dtotal[5];
+  int64_t nonfinite;
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque */
+
+/* Bytes of device memory the populations of `p` need (35 arrays, padded).
+ * Returns 0 if p is invalid. */
+size_t lbm_state_bytes(const lbm_params* p);
+
+/* Validate p, allocate the population buffer on the current HIP device and bind the
+ * context to `hip_stream` (a hipStream_t; NULL creates a private stream, which the
+ * context destroys).  EINVAL: dims < 1, a zero-gradient axis with fewer than 2
+ * cells, omega outside (0, 2], unequal momentum omegas, non-finite or non-positive
+ * gamma-1, mu_ref, T_ref, rho_min, or negative p_min, layout_pad < 0, unknown enum.
+ * ENOMEM: device allocation failed.  On failure *out is NULL. */
+lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out);
+
+/* As lbm_create, but the populations live in the caller's device buffer
+ * `dev_buf` of `bytes` bytes (>= lbm_state_bytes(p), 256-byte aligned), e.g. the
+ * storage of a torch tensor; the caller keeps ownership and must keep it alive
+ * until lbm_destroy. */
+lbm_status lbm_create_in(const lbm_params* p, void* dev_buf, size_t bytes, void* hip_stream,
+                         lbm_ctx** out);
+
+/* Set the state to the equilibrium of Q with the advective flux only (no
+ * non-equilibrium part) and reset the step counter to 0.  Q: host array
+ * [5][nz][ny][nx] of doubles, lattice units, field order (rho, rho u_x, rho u_y,
+ * rho u_z, E).  Synchronises the stream before returning. */
+lbm_status lbm_init_fields(lbm_ctx* ctx, const double* Q);
+
+/* Same, with Q already in device memory (float64, same layout); asynchronous. */
+lbm_status lbm_init_fields_device(lbm_ctx* ctx, const double* Q_dev);
+
+/* Enqueue n >= 0 collide-and-stream steps on the context's stream (asynchronous).
+ * If diag_every > 0, every step whose index t (completed steps before it) satisfies
+ * t % diag_every == 0 also produces a diagnostic record (see lbm_diagnostics).
+ * ESTATE before initialisation. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n, int32_t diag_every);
+
+/* Conserved fields of the current state (post-streaming, i.e. the state after the
+ * completed steps) into the host array Q_out [5][nz][ny][nx] (doubles).
+ * Synchronises the stream. */
+lbm_status lbm_moments(lbm_ctx* ctx, double* Q_out);
+
+/* Same into device memory (float64, same layout); asynchronous. */
+lbm_status lbm_moments_device(lbm_ctx* ctx, double* Q_dev);
+
+/* Copy out, oldest first, up to `max` diagnostic records produced since the last
+ * call and discard them; *count receives the number written.  Synchronises the
+ * stream.  Returns EDIVERGED (after filling the records) if any returned record
+ * has nonfinite > 0. */
+lbm_status lbm_diagnostics(lbm_ctx* ctx, lbm_diag* out, int32_t max, int32_t* count);
+
+/* Checkpoint: the 35 populations of every cell in canonical order (the stored
+ * shifted value of direction i of field k at cell x after the completed steps,
+ * independent of the AA parity) into the host array f[35][nz][ny][nx] (floats),
+ * and the step counter.  Synchronises the stream. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, float* f, int64_t* step);
+
+/* Restore a checkpoint written by lbm_get_populations (same params).  FP16 storage
+ * rounds to nearest even.  Synchronises the stream. */
+lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
+
+/* Launch shape of the collide-and-stream kernel: `block` threads per block (a
+ * multiple of 64 in [64, 1024]; default 256) and nontemporal loads/stores on or
+ * off (default off).  Results do not depend on either.  EINVAL otherwise. */
+lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t nontemporal);
+
+/* Completed steps. */
+lbm_status lbm_get_step(lbm_ctx* ctx, int64_t* step);
+
+/* Release the context (waits for its stream first).  NULL is a no-op. */
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* Achievable HBM bandwidth: a streaming copy of `bytes` bytes (read + write)
+ * repeated `iters` times on a private stream; *gbps receives (2 * bytes) / time of
+ * the fastest repetition in GB/s.  Allocates and frees its own buffers. */
+lbm_status lbm_bw_probe(size_t bytes, int32_t iters, double* gbps);
+
+/* Description of the last failure on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRLBM_H */

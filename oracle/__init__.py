@@ -78,6 +78,7 @@ def _load():
     lib.ora_run.restype = ctypes.c_int64
     lib.ora_cell_info_size.restype = ctypes.c_int32
     lib.ora_params_size.restype = ctypes.c_int32
+    lib.ora_num_threads.restype = ctypes.c_int32
     if lib.ora_cell_info_size() != ctypes.sizeof(OraCellInfo):
         raise RuntimeError("oracle cell-info layout mismatch")
     if lib.ora_params_size() != ctypes.sizeof(OraParams):
@@ -179,3 +180,8 @@ def run(p: dict, f, nsteps: int, diag_every: int = 0):
     d = np.zeros((max(rows, 1), 9))
     r = lib.ora_run(ctypes.byref(P), _ptr(a), _ptr(w), int(nsteps), int(diag_every), _ptr(d))
     return a, d[:r]
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel cell loop uses (OpenMP)."""
+    return int(_load().ora_num_threads())

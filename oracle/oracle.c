@@ -45,6 +45,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_Q 7
 #define ORA_NF 5
@@ -85,11 +88,13 @@ typedef struct {
 } ora_cell_info;
 
 /* ---------------------------------------------------------------- viscosity law */
-/* Sutherland law of Listing 1 with T_S = 0.4042: mu(T_ref) = mu_ref.              */
-static double ora_mu(const ora_params* P, double T) {
-  if (P->mu_law == 0) return P->mu_ref;
+/* Temperature factor mu(T)/mu_ref of the Sutherland law of Listing 1 (T_S = 0.4042),
+ * equal to 1 at T_ref; 1 for the constant law.  Listing 1 scales the conductivity by
+ * the same factor, so it stays defined for an inviscid set-up (mu_ref = 0). */
+static double ora_mu_ratio(const ora_params* P, double T) {
+  if (P->mu_law == 0) return 1.0;
   double t = T / P->T_ref;
-  return P->mu_ref * (1.0 + P->T_S) * pow(t, 1.5) / (t + P->T_S);
+  return (1.0 + P->T_S) * pow(t, 1.5) / (t + P->T_S);
 }
 
 /* ------------------------------------------------ dense diffusive-flux Jacobian */
@@ -229,8 +234,9 @@ void ora_collide(const ora_params* P, const double* f_in, double* f_out, ora_cel
   /* line 2: primitives with positivity floors */
   ora_primitives(P, I->Q, &I->rho_f, I->u, &I->k2, &I->p, &I->T);
   const double rho = I->rho_f;
-  I->mu = ora_mu(P, I->T);
-  I->kappa = P->kappa_ref * I->mu / P->mu_ref;
+  const double ratio = ora_mu_ratio(P, I->T);
+  I->mu = P->mu_ref * ratio;
+  I->kappa = P->kappa_ref * ratio;
   I->nu = I->mu / rho;
 
   /* line 3: non-equilibrium first moment against the advective flux (eq. 3) */
@@ -443,6 +449,19 @@ int64_t ora_run(const ora_params* P, double* f, double* work, int64_t nsteps, in
   }
   if (a != f) memcpy(f, a, sizeof(double) * 35 * N);
   return rows;
+}
+
+/* Threads an OpenMP parallel region of the step uses. */
+int32_t ora_num_threads(void) {
+  int32_t n = 1;
+#ifdef _OPENMP
+#pragma omp parallel
+  {
+#pragma omp single
+    n = (int32_t)omp_get_num_threads();
+  }
+#endif
+  return n;
 }
 
 /* Size of the per-cell info record (lets the Python side check its mirror). */

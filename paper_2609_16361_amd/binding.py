@@ -1,0 +1,286 @@
+"""ctypes binding of libgrlbm.so (the C ABI of include/grlbm.h), same names.
+
+Argument marshalling only: every step of the solver runs in the HIP library.  The
+library is loaded on first use; if it is missing this module raises instead of
+falling back to anything else.
+
+A parameter dict (lattice units, the keys produced by `inputs`) converts to
+`lbm_params` with `make_params`.  `Solver` is a small convenience wrapper that owns a
+context and checks every status.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrlbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
+                -4: "LBM_EDIVERGED", -5: "LBM_ESTATE"}
+LBM_STORE_F32, LBM_STORE_F16 = 0, 1
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc", ctypes.c_int32 * 3),
+        ("collision", ctypes.c_int32), ("storage", ctypes.c_int32), ("mu_law", ctypes.c_int32),
+        ("layout_pad", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("mu_ref", ctypes.c_double), ("kappa_ref", ctypes.c_double),
+        ("T_ref", ctypes.c_double), ("T_S", ctypes.c_double),
+        ("omega", ctypes.c_double * 5),
+        ("sensor_gain", ctypes.c_double), ("J_min", ctypes.c_double), ("omega_min", ctypes.c_double),
+        ("rho_min", ctypes.c_double), ("p_min", ctypes.c_double),
+        ("rho_ref", ctypes.c_double), ("E_ref", ctypes.c_double),
+    ]
+
+
+class lbm_diag(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64),
+        ("Ek", ctypes.c_double), ("eps_s", ctypes.c_double), ("eps_d", ctypes.c_double),
+        ("dtotal", ctypes.c_double * 5),
+        ("nonfinite", ctypes.c_int64),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+SIGNATURES = {
+    "lbm_state_bytes": (ctypes.c_size_t, [_P(lbm_params)]),
+    "lbm_create": (ctypes.c_int, [_P(lbm_params), _vp, _P(_vp)]),
+    "lbm_create_in": (ctypes.c_int, [_P(lbm_params), _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "lbm_init_fields": (ctypes.c_int, [_vp, _P(ctypes.c_double)]),
+    "lbm_init_fields_device": (ctypes.c_int, [_vp, _vp]),
+    "lbm_step": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int32]),
+    "lbm_moments": (ctypes.c_int, [_vp, _P(ctypes.c_double)]),
+    "lbm_moments_device": (ctypes.c_int, [_vp, _vp]),
+    "lbm_diagnostics": (ctypes.c_int, [_vp, _P(lbm_diag), ctypes.c_int32, _P(ctypes.c_int32)]),
+    "lbm_get_populations": (ctypes.c_int, [_vp, _P(ctypes.c_float), _P(ctypes.c_int64)]),
+    "lbm_set_populations": (ctypes.c_int, [_vp, _P(ctypes.c_float), ctypes.c_int64]),
+    "lbm_set_launch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_get_step": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
+    "lbm_destroy": (ctypes.c_int, [_vp]),
+    "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_double)]),
+    "lbm_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises FileNotFoundError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with paper_2609_16361_amd.build.build() "
+            "(there is no fallback implementation)")
+    # PyTorch ships its own HIP runtime with the same soname.  Loading torch first
+    # makes libgrlbm.so bind to that runtime, so one process never holds two HIP
+    # runtimes (which leaves whichever initialises second without a device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, where):
+    if status != LBM_OK:
+        msg = load().lbm_last_error().decode(errors="replace")
+        raise LbmError(status, where, msg)
+
+
+def make_params(p: dict, storage: int | None = None, layout_pad: int = 0) -> lbm_params:
+    o = lbm_params()
+    o.nx, o.ny, o.nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
+    for a in range(3):
+        o.bc[a] = int(p["bc"][a])
+    o.collision = int(p["collision"])
+    o.storage = int(p.get("storage", LBM_STORE_F32) if storage is None else storage)
+    o.mu_law = int(p["mu_law"])
+    o.layout_pad = int(p.get("layout_pad", layout_pad))
+    o.gamma = float(p["gamma"])
+    o.mu_ref = float(p["mu_ref"])
+    o.kappa_ref = float(p["kappa_ref"])
+    o.T_ref = float(p["T_ref"])
+    o.T_S = float(p["T_S"])
+    for k in range(5):
+        o.omega[k] = float(p["omega"][k])
+    o.sensor_gain = float(p["sensor_gain"])
+    o.J_min = float(p["J_min"])
+    o.omega_min = float(p["omega_min"])
+    o.rho_min = float(p["rho_min"])
+    o.p_min = float(p["p_min"])
+    o.rho_ref = float(p["rho_ref"])
+    o.E_ref = float(p["E_ref"])
+    return o
+
+
+# ---------------------------------------------------------- C names, thin wrappers
+def lbm_state_bytes(params: lbm_params) -> int:
+    return int(load().lbm_state_bytes(ctypes.byref(params)))
+
+
+def lbm_create(params: lbm_params, stream: int | None = None) -> int:
+    h = _vp()
+    _check(load().lbm_create(ctypes.byref(params), stream, ctypes.byref(h)), "lbm_create")
+    return h.value
+
+
+def lbm_create_in(params: lbm_params, dev_ptr: int, nbytes: int, stream: int | None = None) -> int:
+    h = _vp()
+    _check(load().lbm_create_in(ctypes.byref(params), dev_ptr, nbytes, stream, ctypes.byref(h)),
+           "lbm_create_in")
+    return h.value
+
+
+def lbm_init_fields(ctx: int, Q: np.ndarray) -> None:
+    q = np.ascontiguousarray(Q, dtype=np.float64)
+    _check(load().lbm_init_fields(ctx, q.ctypes.data_as(_P(ctypes.c_double))), "lbm_init_fields")
+
+
+def lbm_init_fields_device(ctx: int, dev_ptr: int) -> None:
+    _check(load().lbm_init_fields_device(ctx, dev_ptr), "lbm_init_fields_device")
+
+
+def lbm_step(ctx: int, n: int, diag_every: int = 0) -> None:
+    _check(load().lbm_step(ctx, int(n), int(diag_every)), "lbm_step")
+
+
+def lbm_moments(ctx: int, shape) -> np.ndarray:
+    out = np.empty((5,) + tuple(shape), dtype=np.float64)
+    _check(load().lbm_moments(ctx, out.ctypes.data_as(_P(ctypes.c_double))), "lbm_moments")
+    return out
+
+
+def lbm_moments_device(ctx: int, dev_ptr: int) -> None:
+    _check(load().lbm_moments_device(ctx, dev_ptr), "lbm_moments_device")
+
+
+def lbm_diagnostics(ctx: int, max_records: int = 4096):
+    """Returns (records as a list of dicts, status).  EDIVERGED is returned, not
+    raised, so callers can inspect the records."""
+    buf = (lbm_diag * max_records)()
+    cnt = ctypes.c_int32(0)
+    st = load().lbm_diagnostics(ctx, buf, max_records, ctypes.byref(cnt))
+    if st not in (LBM_OK, LBM_EDIVERGED):
+        _check(st, "lbm_diagnostics")
+    recs = []
+    for i in range(cnt.value):
+        d = buf[i]
+        recs.append(dict(step=d.step, Ek=d.Ek, eps_s=d.eps_s, eps_d=d.eps_d,
+                         dtotal=list(d.dtotal), nonfinite=d.nonfinite))
+    return recs, st
+
+
+def lbm_get_populations(ctx: int, shape):
+    f = np.empty((35,) + tuple(shape), dtype=np.float32)
+    step = ctypes.c_int64(0)
+    _check(load().lbm_get_populations(ctx, f.ctypes.data_as(_P(ctypes.c_float)), ctypes.byref(step)),
+           "lbm_get_populations")
+    return f, step.value
+
+
+def lbm_set_populations(ctx: int, f: np.ndarray, step: int) -> None:
+    ff = np.ascontiguousarray(f, dtype=np.float32)
+    _check(load().lbm_set_populations(ctx, ff.ctypes.data_as(_P(ctypes.c_float)), int(step)),
+           "lbm_set_populations")
+
+
+def lbm_set_launch(ctx: int, block: int, nontemporal: bool) -> None:
+    _check(load().lbm_set_launch(ctx, int(block), int(bool(nontemporal))), "lbm_set_launch")
+
+
+def lbm_get_step(ctx: int) -> int:
+    s = ctypes.c_int64(0)
+    _check(load().lbm_get_step(ctx, ctypes.byref(s)), "lbm_get_step")
+    return s.value
+
+
+def lbm_destroy(ctx: int) -> None:
+    _check(load().lbm_destroy(ctx), "lbm_destroy")
+
+
+def lbm_bw_probe(nbytes: int, iters: int = 10) -> float:
+    g = ctypes.c_double(0.0)
+    _check(load().lbm_bw_probe(int(nbytes), int(iters), ctypes.byref(g)), "lbm_bw_probe")
+    return g.value
+
+
+def lbm_last_error() -> str:
+    return load().lbm_last_error().decode(errors="replace")
+
+
+# ----------------------------------------------------------------- convenience
+class Solver:
+    """One context.  `stream` is a hipStream_t handle (e.g.
+    torch.cuda.current_stream().cuda_stream) or None for a private stream."""
+
+    def __init__(self, params: dict, stream: int | None = None, storage: int | None = None,
+                 block: int | None = None, nontemporal: bool | None = None, layout_pad: int = 0):
+        self.params = dict(params)
+        self.cparams = make_params(params, storage=storage, layout_pad=layout_pad)
+        self.shape = (self.cparams.nz, self.cparams.ny, self.cparams.nx)
+        self.ctx = lbm_create(self.cparams, stream)
+        if block is not None or nontemporal is not None:
+            lbm_set_launch(self.ctx, block or 256, bool(nontemporal))
+
+    def init(self, Q):
+        lbm_init_fields(self.ctx, np.asarray(Q, dtype=np.float64).reshape((5,) + self.shape))
+
+    def step(self, n, diag_every=0):
+        lbm_step(self.ctx, n, diag_every)
+
+    def moments(self):
+        return lbm_moments(self.ctx, self.shape)
+
+    def diagnostics(self):
+        return lbm_diagnostics(self.ctx)
+
+    def populations(self):
+        return lbm_get_populations(self.ctx, self.shape)
+
+    def set_populations(self, f, step):
+        lbm_set_populations(self.ctx, f, step)
+
+    @property
+    def step_count(self):
+        return lbm_get_step(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,35 @@
+"""Compile the HIP library libgrlbm.so for gfx950 with hipcc (in-tree).
+
+The library holds every kernel of the solver and the C ABI of include/grlbm.h.
+Packed-FP32 instructions are disabled for all device code.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libgrlbm.so")
+SOURCES = ["grlbm_kernels.hip", "grlbm_api.hip"]
+ARCH = "gfx950"
+
+
+def hipcc_cmd(out, extra=()):
+    return (["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wall", "-Wno-unused-function", f"-I{os.path.join(HERE, '..', 'include')}"]
+            + list(extra) + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", out])
+
+
+def build(verbose: bool = False) -> str:
+    """Always recompile; returns the path of the shared library."""
+    tmp = LIB + ".tmp"
+    cmd = hipcc_cmd(tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

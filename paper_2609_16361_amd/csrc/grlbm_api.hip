@@ -1,0 +1,483 @@
+// grlbm_api.hip -- the C ABI of include/grlbm.h: validation, device memory,
+// stream binding, step scheduling and the diagnostic record queue.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/grlbm.h"
+#include "grlbm_internal.h"
+
+using grlbm::Coll;
+using grlbm::Grid;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+constexpr int kDiagVals = 9;
+constexpr int32_t kRingCap = 1024;
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+lbm_status validate(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(LBM_EINVAL, "dims must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+  const int32_t dims[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_ZERO_GRADIENT)
+      return fail(LBM_EINVAL, "bc[%d] = %d is not an lbm_bc", a, p->bc[a]);
+    if (p->bc[a] == LBM_BC_ZERO_GRADIENT && dims[a] < 2)
+      return fail(LBM_EINVAL, "zero-gradient axis %d needs >= 2 cells (got %d)", a, dims[a]);
+  }
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  if (N > (int64_t)INT32_MAX / 2)
+    return fail(LBM_EINVAL, "grid of %lld cells exceeds the 32-bit cell index range", (long long)N);
+  if (p->collision != LBM_COLL_RLB_SENSOR && p->collision != LBM_COLL_BGK)
+    return fail(LBM_EINVAL, "collision = %d is not an lbm_collision", p->collision);
+  if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F16)
+    return fail(LBM_EINVAL, "storage = %d is not an lbm_storage", p->storage);
+  if (p->mu_law != LBM_MU_CONSTANT && p->mu_law != LBM_MU_SUTHERLAND)
+    return fail(LBM_EINVAL, "mu_law = %d is not an lbm_mu_law", p->mu_law);
+  if (p->layout_pad < 0) return fail(LBM_EINVAL, "layout_pad must be >= 0");
+  if (!finite_pos(p->gamma - 1.0)) return fail(LBM_EINVAL, "gamma must be finite and > 1");
+  if (!(std::isfinite(p->mu_ref) && p->mu_ref >= 0.0)) return fail(LBM_EINVAL, "mu_ref must be >= 0");
+  if (!(std::isfinite(p->kappa_ref) && p->kappa_ref >= 0.0))
+    return fail(LBM_EINVAL, "kappa_ref must be >= 0");
+  if (p->mu_law == LBM_MU_SUTHERLAND) {
+    if (!finite_pos(p->T_ref)) return fail(LBM_EINVAL, "T_ref must be > 0");
+    if (!(std::isfinite(p->T_S) && p->T_S >= 0.0)) return fail(LBM_EINVAL, "T_S must be >= 0");
+  }
+  for (int k = 0; k < 5; ++k)
+    if (!(std::isfinite(p->omega[k]) && p->omega[k] > 0.0 && p->omega[k] <= 2.0))
+      return fail(LBM_EINVAL, "omega[%d] = %g outside (0, 2]", k, p->omega[k]);
+  if (p->omega[1] != p->omega[2] || p->omega[1] != p->omega[3])
+    return fail(LBM_EINVAL, "the three momentum relaxation frequencies must be equal");
+  if (!(std::isfinite(p->sensor_gain) && p->sensor_gain >= 0.0))
+    return fail(LBM_EINVAL, "sensor_gain must be >= 0");
+  if (!std::isfinite(p->J_min)) return fail(LBM_EINVAL, "J_min must be finite");
+  if (!(std::isfinite(p->omega_min) && p->omega_min > 0.0 && p->omega_min <= 2.0))
+    return fail(LBM_EINVAL, "omega_min outside (0, 2]");
+  if (!finite_pos(p->rho_min)) return fail(LBM_EINVAL, "rho_min must be > 0");
+  if (!(std::isfinite(p->p_min) && p->p_min >= 0.0)) return fail(LBM_EINVAL, "p_min must be >= 0");
+  if (!std::isfinite(p->rho_ref) || !std::isfinite(p->E_ref))
+    return fail(LBM_EINVAL, "rho_ref and E_ref must be finite");
+  return LBM_OK;
+}
+
+int64_t slot_stride(const lbm_params* p) {
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  const int64_t el = p->storage == LBM_STORE_F16 ? 2 : 4;
+  const int64_t align = 256 / el;  // arrays start on 256-byte boundaries
+  const int64_t s = N + p->layout_pad;
+  return (s + align - 1) / align * align;
+}
+
+size_t state_bytes(const lbm_params* p) {
+  const int64_t el = p->storage == LBM_STORE_F16 ? 2 : 4;
+  return (size_t)(slot_stride(p) * 35 * el);
+}
+
+Coll make_coll(const lbm_params* p) {
+  Coll c;
+  c.om[0] = (float)p->omega[0];
+  c.om[1] = (float)p->omega[1];
+  c.om[2] = (float)p->omega[4];
+  c.gm1 = (float)(p->gamma - 1.0);
+  c.mu_ref = (float)p->mu_ref;
+  c.kappa_ref = (float)p->kappa_ref;
+  c.suth_c = (float)(1.0 + p->T_S);
+  c.inv_T_ref = p->T_ref > 0.0 ? (float)(1.0 / p->T_ref) : 0.0f;
+  c.T_S = (float)p->T_S;
+  c.gain = (float)p->sensor_gain;
+  c.J_min = (float)p->J_min;
+  c.om_min = (float)p->omega_min;
+  c.rho_min = (float)p->rho_min;
+  c.p_min = (float)p->p_min;
+  c.rho_ref = (float)p->rho_ref;
+  c.E_ref = (float)p->E_ref;
+  c.sutherland = p->mu_law == LBM_MU_SUTHERLAND ? 1 : 0;
+  return c;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p{};
+  Grid g{};
+  Coll c{};
+  int64_t N = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  void* F = nullptr;
+  size_t F_bytes = 0;
+  bool own_F = false;
+  int64_t step = 0;
+  bool ready = false;
+  int block = 256;
+  bool nt = false;
+  float* partials = nullptr;
+  int64_t partials_blocks = 0;
+  float* ring = nullptr;
+  int32_t ring_used = 0;
+  std::vector<int64_t> ring_steps;
+  std::deque<lbm_diag> done;
+};
+
+namespace {
+
+lbm_status ensure_partials(lbm_ctx* c) {
+  const int64_t nb = grlbm::step_blocks(c->g, c->block);
+  if (nb <= c->partials_blocks) return LBM_OK;
+  if (c->partials) HIP_TRY(hipFree(c->partials));
+  c->partials = nullptr;
+  c->partials_blocks = 0;
+  if (hipMalloc(&c->partials, (size_t)nb * kDiagVals * sizeof(float)) != hipSuccess)
+    return fail(LBM_ENOMEM, "hipMalloc of %lld diagnostic partials failed", (long long)nb);
+  c->partials_blocks = nb;
+  return LBM_OK;
+}
+
+lbm_status drain_ring(lbm_ctx* c) {
+  if (c->ring_used == 0) return LBM_OK;
+  std::vector<float> h((size_t)c->ring_used * kDiagVals);
+  HIP_TRY(hipMemcpyAsync(h.data(), c->ring, h.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int32_t r = 0; r < c->ring_used; ++r) {
+    const float* v = &h[(size_t)r * kDiagVals];
+    lbm_diag d{};
+    d.step = c->ring_steps[r];
+    d.Ek = v[0];
+    d.eps_s = v[1];
+    d.eps_d = v[2];
+    for (int k = 0; k < 5; ++k) d.dtotal[k] = v[3 + k];
+    d.nonfinite = (int64_t)std::llround((double)v[8]);
+    c->done.push_back(d);
+  }
+  c->ring_used = 0;
+  c->ring_steps.clear();
+  return LBM_OK;
+}
+
+lbm_status create_common(const lbm_params* p, void* buf, size_t bytes, void* stream, lbm_ctx** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status st = validate(p);
+  if (st != LBM_OK) return st;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_ENOMEM, "host allocation of the context failed");
+  c->p = *p;
+  c->N = (int64_t)p->nx * p->ny * p->nz;
+  c->g.nx = p->nx;
+  c->g.ny = p->ny;
+  c->g.nz = p->nz;
+  c->g.zg_x = p->bc[0] == LBM_BC_ZERO_GRADIENT;
+  c->g.zg_y = p->bc[1] == LBM_BC_ZERO_GRADIENT;
+  c->g.zg_z = p->bc[2] == LBM_BC_ZERO_GRADIENT;
+  c->g.S = slot_stride(p);
+  c->c = make_coll(p);
+  c->F_bytes = state_bytes(p);
+  auto bail = [&](lbm_status s) {
+    lbm_destroy(c);
+    return s;
+  };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(fail(LBM_EDEVICE, "no HIP device"));
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) return bail(fail(LBM_EDEVICE, "hipStreamCreate failed"));
+    c->own_stream = true;
+  }
+  if (buf) {
+    if (bytes < c->F_bytes)
+      return bail(fail(LBM_EINVAL, "buffer of %zu bytes is smaller than the %zu the state needs", bytes,
+                       c->F_bytes));
+    if (((uintptr_t)buf) % 256 != 0) return bail(fail(LBM_EINVAL, "buffer is not 256-byte aligned"));
+    c->F = buf;
+  } else {
+    if (hipMalloc(&c->F, c->F_bytes) != hipSuccess)
+      return bail(fail(LBM_ENOMEM, "hipMalloc of %zu population bytes failed", c->F_bytes));
+    c->own_F = true;
+  }
+  if (hipMalloc(&c->ring, (size_t)kRingCap * kDiagVals * sizeof(float)) != hipSuccess)
+    return bail(fail(LBM_ENOMEM, "hipMalloc of the diagnostic ring failed"));
+  c->ring_steps.reserve(kRingCap);
+  *out = c;
+  return LBM_OK;
+}
+
+template <typename T>
+lbm_status dev_alloc(T** p, size_t count, const char* what) {
+  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess)
+    return fail(LBM_ENOMEM, "hipMalloc of %zu bytes (%s) failed", count * sizeof(T), what);
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_state_bytes(const lbm_params* p) {
+  if (validate(p) != LBM_OK) return 0;
+  return state_bytes(p);
+}
+
+lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out) {
+  return create_common(p, nullptr, 0, hip_stream, out);
+}
+
+lbm_status lbm_create_in(const lbm_params* p, void* dev_buf, size_t bytes, void* hip_stream,
+                         lbm_ctx** out) {
+  if (!dev_buf) {
+    if (out) *out = nullptr;
+    return fail(LBM_EINVAL, "dev_buf is NULL");
+  }
+  return create_common(p, dev_buf, bytes, hip_stream, out);
+}
+
+lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t nontemporal) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (block < 64 || block > 1024 || block % 64 != 0)
+    return fail(LBM_EINVAL, "block = %d must be a multiple of 64 in [64, 1024]", block);
+  c->block = block;
+  c->nt = nontemporal != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields_device(lbm_ctx* c, const double* Q_dev) {
+  if (!c || !Q_dev) return fail(LBM_EINVAL, "ctx or Q is NULL");
+  HIP_TRY(grlbm::launch_init(c->F, c->p.storage == LBM_STORE_F16, c->g, c->c, Q_dev, c->N, c->stream));
+  c->step = 0;
+  c->ready = true;
+  c->ring_used = 0;
+  c->ring_steps.clear();
+  c->done.clear();
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, const double* Q) {
+  if (!c || !Q) return fail(LBM_EINVAL, "ctx or Q is NULL");
+  double* d = nullptr;
+  lbm_status st = dev_alloc(&d, (size_t)5 * c->N, "initial fields");
+  if (st != LBM_OK) return st;
+  hipError_t e = hipMemcpyAsync(d, Q, (size_t)5 * c->N * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) {
+    st = lbm_init_fields_device(c, d);
+    e = hipStreamSynchronize(c->stream);
+  }
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "initialisation failed: %s", hipGetErrorString(e));
+  return st;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n, int32_t diag_every) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
+  if (diag_every < 0) return fail(LBM_EINVAL, "diag_every < 0");
+  if (!c->ready) return fail(LBM_ESTATE, "lbm_step before lbm_init_fields or lbm_set_populations");
+  grlbm::StepLaunch L;
+  L.F = c->F;
+  L.g = c->g;
+  L.c = c->c;
+  L.block = c->block;
+  L.coll = c->p.collision;
+  L.f16 = c->p.storage == LBM_STORE_F16;
+  L.nt = c->nt;
+  L.partials = nullptr;
+  if (diag_every > 0) {
+    lbm_status st = ensure_partials(c);
+    if (st != LBM_OK) return st;
+  }
+  const int64_t nb = grlbm::step_blocks(c->g, c->block);
+  for (int64_t s = 0; s < n; ++s) {
+    const int64_t t = c->step;
+    const bool diag = diag_every > 0 && (t % diag_every) == 0;
+    L.odd = (t & 1) != 0;
+    L.diag = diag;
+    if (diag) {
+      if (c->ring_used == kRingCap) {
+        lbm_status st = drain_ring(c);
+        if (st != LBM_OK) return st;
+      }
+      L.partials = c->partials;
+    }
+    HIP_TRY(grlbm::launch_step(L, c->stream));
+    if (diag) {
+      HIP_TRY(grlbm::launch_finalize(c->partials, nb, c->ring + (size_t)c->ring_used * kDiagVals, c->stream));
+      c->ring_steps.push_back(t);
+      ++c->ring_used;
+    }
+    ++c->step;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments_device(lbm_ctx* c, double* Q_dev) {
+  if (!c || !Q_dev) return fail(LBM_EINVAL, "ctx or Q is NULL");
+  if (!c->ready) return fail(LBM_ESTATE, "no state yet");
+  HIP_TRY(grlbm::launch_gather(c->F, c->p.storage == LBM_STORE_F16, c->g, c->c, c->N, (c->step & 1) != 0, 1,
+                               nullptr, Q_dev, c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, double* Q_out) {
+  if (!c || !Q_out) return fail(LBM_EINVAL, "ctx or Q_out is NULL");
+  if (!c->ready) return fail(LBM_ESTATE, "no state yet");
+  double* d = nullptr;
+  lbm_status st = dev_alloc(&d, (size_t)5 * c->N, "moments");
+  if (st != LBM_OK) return st;
+  st = lbm_moments_device(c, d);
+  hipError_t e = hipSuccess;
+  if (st == LBM_OK) {
+    e = hipMemcpyAsync(Q_out, d, (size_t)5 * c->N * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "moments readout failed: %s", hipGetErrorString(e));
+  return st;
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* c, lbm_diag* out, int32_t max, int32_t* count) {
+  if (!c || !count || (max > 0 && !out)) return fail(LBM_EINVAL, "NULL argument");
+  *count = 0;
+  lbm_status st = drain_ring(c);
+  if (st != LBM_OK) return st;
+  bool bad = false;
+  while (*count < max && !c->done.empty()) {
+    out[*count] = c->done.front();
+    bad |= out[*count].nonfinite > 0;
+    c->done.pop_front();
+    ++*count;
+  }
+  if (bad) return fail(LBM_EDIVERGED, "non-finite populations in a diagnostic record");
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, float* f, int64_t* step) {
+  if (!c || !f) return fail(LBM_EINVAL, "ctx or f is NULL");
+  if (!c->ready) return fail(LBM_ESTATE, "no state yet");
+  float* d = nullptr;
+  lbm_status st = dev_alloc(&d, (size_t)35 * c->N, "populations");
+  if (st != LBM_OK) return st;
+  hipError_t e = grlbm::launch_gather(c->F, c->p.storage == LBM_STORE_F16, c->g, c->c, c->N,
+                                      (c->step & 1) != 0, 0, d, nullptr, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(f, d, (size_t)35 * c->N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "population readout failed: %s", hipGetErrorString(e));
+  if (step) *step = c->step;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const float* f, int64_t step) {
+  if (!c || !f) return fail(LBM_EINVAL, "ctx or f is NULL");
+  if (step < 0) return fail(LBM_EINVAL, "step < 0");
+  float* d = nullptr;
+  lbm_status st = dev_alloc(&d, (size_t)35 * c->N, "populations");
+  if (st != LBM_OK) return st;
+  hipError_t e = hipMemcpyAsync(d, f, (size_t)35 * c->N * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = grlbm::launch_scatter(c->F, c->p.storage == LBM_STORE_F16, c->g, c->N, (step & 1) != 0, d, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "population restore failed: %s", hipGetErrorString(e));
+  c->step = step;
+  c->ready = true;
+  c->ring_used = 0;
+  c->ring_steps.clear();
+  c->done.clear();
+  return LBM_OK;
+}
+
+lbm_status lbm_get_step(lbm_ctx* c, int64_t* step) {
+  if (!c || !step) return fail(LBM_EINVAL, "NULL argument");
+  *step = c->step;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  lbm_status st = LBM_OK;
+  if (c->stream && hipStreamSynchronize(c->stream) != hipSuccess)
+    st = fail(LBM_EDEVICE, "stream synchronisation failed during destroy");
+  if (c->own_F && c->F) (void)hipFree(c->F);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->ring) (void)hipFree(c->ring);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return st;
+}
+
+lbm_status lbm_bw_probe(size_t bytes, int32_t iters, double* gbps) {
+  if (!gbps || bytes < 16 || iters < 1) return fail(LBM_EINVAL, "bad bw_probe arguments");
+  bytes = bytes / 16 * 16;
+  void *a = nullptr, *b = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  lbm_status st = LBM_OK;
+  float best = 1e30f;
+  if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+    st = fail(LBM_ENOMEM, "hipMalloc of 2 x %zu bytes failed", bytes);
+    goto done;
+  }
+  if (hipStreamCreate(&s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    st = fail(LBM_EDEVICE, "stream/event creation failed");
+    goto done;
+  }
+  if (hipMemsetAsync(a, 0, bytes, s) != hipSuccess || grlbm::launch_copy(a, b, (int64_t)bytes, s) != hipSuccess) {
+    st = fail(LBM_EDEVICE, "copy kernel failed");
+    goto done;
+  }
+  for (int32_t it = 0; it < iters; ++it) {
+    float ms = 0.0f;
+    if (hipEventRecord(e0, s) != hipSuccess || grlbm::launch_copy(a, b, (int64_t)bytes, s) != hipSuccess ||
+        hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(LBM_EDEVICE, "timed copy failed");
+      goto done;
+    }
+    if (ms < best) best = ms;
+  }
+  *gbps = 2.0 * (double)bytes / (best * 1e-3) / 1e9;
+done:
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (s) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  return st;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

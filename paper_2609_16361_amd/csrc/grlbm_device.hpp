@@ -1,0 +1,317 @@
+// grlbm_device.hpp -- device-side building blocks of the five-field update for
+// gfx950: lattice addressing of the in-place AA pattern and the register-resident
+// collision of Algorithm 1.
+//
+// Layout.  Populations are 35 arrays ("slots"), slot s = 7 k + i for field k
+// (rho, rho u_x, rho u_y, rho u_z, E) and D3Q7 direction i (0, +x, -x, +y, -y, +z,
+// -z); array s starts at element s * S, and cell (x, y, z) sits at element
+// x + nx (y + ny z) of every array.  Each stored value is g = f - w_i Q_ref,k.
+//
+// AA pattern (one buffer, updated in place).  At even parity slot i of cell x holds
+// f_i(x).  An even step reads the cell's own slots and writes f*_i to its own slot
+// opposite(i).  The odd step reads f_i(x) = f*_i(x - c_i) from slot opposite(i) of
+// x - c_i and writes f*_i(x) to slot i of x + c_i, which restores even parity.  In
+// both steps every memory location is read and written by the same lane only.
+//
+// Zero-gradient faces (the ghost beyond the face holds the adjacent cell's own
+// post-collision populations).  For a direction i whose upstream neighbour x - c_i
+// lies beyond such a face:
+//   even step: slot i of x receives f*_i(x) (the ghost copy) instead of
+//              f*_opposite(i)(x), which leaves the domain and is dropped;
+//   odd step:  f_i(x) is read from slot i of x, f*_i(x) is also written to slot i
+//              of x (the ghost copy entering at the next even step), and the
+//              population leaving through the face is dropped.
+// No other lane touches those locations in that step, so the scheme stays
+// race-free; it needs at least two cells along a zero-gradient axis.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grlbm {
+
+constexpr int kQ = 7;
+constexpr int kFields = 5;
+constexpr int kPop = 35;
+
+// Physics constants of one launch, FP32, lattice units.
+struct Coll {
+  float om[3];       // omega of rho, momentum, energy
+  float gm1;         // gamma - 1
+  float mu_ref;      // viscosity at T_ref
+  float kappa_ref;   // conductivity at T_ref
+  float suth_c;      // 1 + T_S, Sutherland prefactor
+  float inv_T_ref, T_S;
+  float gain, J_min, om_min;
+  float rho_min, p_min;
+  float rho_ref, E_ref;
+  int32_t sutherland;
+};
+
+struct Grid {
+  int32_t nx, ny, nz;
+  int32_t zg_x, zg_y, zg_z;  // zero-gradient flags per axis
+  int64_t S;                 // elements between consecutive slot arrays
+};
+
+// Per-lane neighbourhood: the cell index and, for each of the six moving
+// directions, where an odd step reads f_i (slot and cell) and whether the lane sits
+// on a zero-gradient face upstream (lo) or downstream (hi) of that axis.
+struct Nbr {
+  int32_t n;
+  int32_t xm, xp, ym, yp, zm, zp;  // periodic-wrapped neighbour cells
+  bool lo_x, hi_x, lo_y, hi_y, lo_z, hi_z;
+};
+
+__device__ __forceinline__ Nbr make_nbr(const Grid& g, int x, int y, int z) {
+  Nbr b;
+  const int32_t plane = g.nx * g.ny;
+  b.n = x + g.nx * (y + g.ny * z);
+  b.xm = (x == 0) ? b.n + (g.nx - 1) : b.n - 1;
+  b.xp = (x == g.nx - 1) ? b.n - (g.nx - 1) : b.n + 1;
+  b.ym = (y == 0) ? b.n + g.nx * (g.ny - 1) : b.n - g.nx;
+  b.yp = (y == g.ny - 1) ? b.n - g.nx * (g.ny - 1) : b.n + g.nx;
+  b.zm = (z == 0) ? b.n + plane * (g.nz - 1) : b.n - plane;
+  b.zp = (z == g.nz - 1) ? b.n - plane * (g.nz - 1) : b.n + plane;
+  b.lo_x = g.zg_x && x == 0;
+  b.hi_x = g.zg_x && x == g.nx - 1;
+  b.lo_y = g.zg_y && y == 0;
+  b.hi_y = g.zg_y && y == g.ny - 1;
+  b.lo_z = g.zg_z && z == 0;
+  b.hi_z = g.zg_z && z == g.nz - 1;
+  return b;
+}
+
+// Element offset (within field k's block of 7 arrays) of f_i(x) for the read of an
+// odd step, or equally the location of f_i(x) in the state after an odd number of
+// completed steps.  Returns slot * S + cell relative to the field's first array.
+template <bool ZG>
+__device__ __forceinline__ int64_t odd_src(const Grid& g, const Nbr& b, int i) {
+  const int64_t S = g.S;
+  switch (i) {
+    case 1: return (ZG && b.lo_x) ? 1 * S + b.n : 2 * S + b.xm;
+    case 2: return (ZG && b.hi_x) ? 2 * S + b.n : 1 * S + b.xp;
+    case 3: return (ZG && b.lo_y) ? 3 * S + b.n : 4 * S + b.ym;
+    case 4: return (ZG && b.hi_y) ? 4 * S + b.n : 3 * S + b.yp;
+    case 5: return (ZG && b.lo_z) ? 5 * S + b.n : 6 * S + b.zm;
+    case 6: return (ZG && b.hi_z) ? 6 * S + b.n : 5 * S + b.zp;
+    default: return b.n;
+  }
+}
+
+// ---------------------------------------------------------------- storage types
+template <typename T, bool NT>
+__device__ __forceinline__ float ld(const T* p) {
+  if constexpr (NT) {
+    return static_cast<float>(__builtin_nontemporal_load(p));
+  } else {
+    return static_cast<float>(*p);
+  }
+}
+
+template <typename T, bool NT>
+__device__ __forceinline__ void st(T* p, float v) {
+  if constexpr (NT) {
+    __builtin_nontemporal_store(static_cast<T>(v), p);
+  } else {
+    *p = static_cast<T>(v);
+  }
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Per-cell diagnostic densities (Sec. 3.3 channels) of the pre-collision state.
+struct CellDiag {
+  float ek, eps_s, eps_d;
+  float dq[5];
+  float nonfinite;
+};
+
+// --------------------------------------------------------------- the collision
+// Algorithm 1 for one cell on the shifted populations g[35] (post-stream,
+// pre-collision); overwrites g with the post-collision values.
+//   COLL = 0: regularized collision with the compression sensor (Sec. 2.5)
+//   COLL = 1: BGK
+// The reconstruction R of eq. 4 is applied in closed form:
+//   mass:      grad rho = grad~ rho                     (mass row of M is zero)
+//   momentum:  X~ = grad~(rho u) - u (x) grad rho, and only the symmetric-
+//              deviatoric part of X~ is scaled by 1/(1+beta), beta = 2 nu omega/c_s^2
+//              (eq. 6); grad u = X / rho, grad(rho u) = X + u (x) grad rho
+//   energy:    the scalar inversion of eq. 7 with the energy-row blocks of eq. 5
+// followed by the chain rule to grad T.
+template <int COLL, bool DIAG>
+__device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* d) {
+  // line 1: moments (the shift cancels in the first moments)
+  float dq[5], J[5][3];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const float* f = g + 7 * k;
+    dq[k] = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + f[6]);
+    J[k][0] = f[1] - f[2];
+    J[k][1] = f[3] - f[4];
+    J[k][2] = f[5] - f[6];
+  }
+  const float rho = c.rho_ref + dq[0];
+  const float m0 = dq[1], m1 = dq[2], m2 = dq[3];
+  const float E = c.E_ref + dq[4];
+
+  // line 2: primitives with positivity floors
+  const float rf = fmaxf(rho, c.rho_min);
+  const float ir = rcp(rf);
+  const float u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
+  const float k2 = u0 * u0 + u1 * u1 + u2 * u2;
+  const float p = fmaxf(c.gm1 * (E - 0.5f * rf * k2), c.p_min);
+  const float T = p * ir;
+  // Sutherland factor mu(T)/mu_ref; the conductivity scales with the same factor
+  float ratio = 1.0f;
+  if (c.sutherland) {
+    const float t = T * c.inv_T_ref;
+    ratio = c.suth_c * t * __builtin_amdgcn_sqrtf(t) * rcp(t + c.T_S);
+  }
+  const float mu = c.mu_ref * ratio;
+  const float kap = c.kappa_ref * ratio;
+  const float nu = mu * ir;
+
+  // line 3: direct gradients -Pi / (c_s^2 tau) = -4 omega (J - Phi_adv)  (eq. 3)
+  const float a_r = -4.0f * c.om[0], a_m = -4.0f * c.om[1], a_e = -4.0f * c.om[2];
+  const float gr0 = a_r * (J[0][0] - m0);
+  const float gr1 = a_r * (J[0][1] - m1);
+  const float gr2 = a_r * (J[0][2] - m2);
+  const float u[3] = {u0, u1, u2};
+  const float m[3] = {m0, m1, m2};
+  const float gr[3] = {gr0, gr1, gr2};
+  float X[3][3];  // X~ = grad~(rho u) - u (x) grad rho
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const float adv = m[j] * u[cc] + (j == cc ? p : 0.0f);
+      X[j][cc] = a_m * (J[1 + j][cc] - adv) - u[j] * gr[cc];
+    }
+  const float H = E + p;
+  float gE[3];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) gE[cc] = a_e * (J[4][cc] - H * u[cc]);
+
+  // line 4: reconstruction.  Momentum block: scale the symmetric-deviatoric part.
+  const float tr = X[0][0] + X[1][1] + X[2][2];
+  const float beta = 8.0f * nu * c.om[1];
+  const float fb = beta * rcp(1.0f + beta);
+  const float tr3 = tr * (1.0f / 3.0f);
+  float Xs[3][3];  // corrected rho grad u
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const float dev = 0.5f * (X[j][cc] + X[cc][j]) - (j == cc ? tr3 : 0.0f);
+      Xs[j][cc] = X[j][cc] - fb * dev;
+    }
+  // grad(rho u) = Xs + u (x) grad rho
+  float Gm[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) Gm[j][cc] = Xs[j][cc] + u[j] * gr[cc];
+  // energy row (eq. 7): grad E = (grad~E + 4 omega_E (M_Erho grad rho + M_Em grad m))
+  //                               / (1 + 4 omega_E (gamma-1) kappa/rho)
+  const float kr = kap * ir;
+  const float ug = u0 * gr0 + u1 * gr1 + u2 * gr2;
+  const float cr = nu * k2 + kr * (T - 0.5f * c.gm1 * k2);
+  const float trm = Gm[0][0] + Gm[1][1] + Gm[2][2];
+  const float ae4 = 4.0f * c.om[2];
+  const float den = rcp(1.0f + ae4 * c.gm1 * kr);
+  float Bt[3], gradE[3];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    const float bm = Gm[cc][0] * u0 + Gm[cc][1] * u1 + Gm[cc][2] * u2;  // (grad m) u
+    const float bt = Gm[0][cc] * u0 + Gm[1][cc] * u1 + Gm[2][cc] * u2;  // (grad m)^T u
+    Bt[cc] = bt;
+    const float MEr = cr * gr[cc] + nu * (1.0f / 3.0f) * u[cc] * ug;
+    const float MEm = -nu * (bm + bt - (2.0f / 3.0f) * trm * u[cc]) + c.gm1 * kr * bt;
+    gradE[cc] = (gE[cc] + ae4 * (MEr + MEm)) * den;
+  }
+  // chain rule: grad T = (gamma-1)/rho (grad E - (grad m)^T u) + (1/rho)((gamma-1)/2 |u|^2 - T) grad rho
+  const float cT = ir * (0.5f * c.gm1 * k2 - T);
+  const float gTf = c.gm1 * ir;
+  float gT[3];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) gT[cc] = gTf * (gradE[cc] - Bt[cc]) + cT * gr[cc];
+
+  // line 5: compression sensor, s = -div(u)/c_s with c_s = 1/2
+  const float theta = tr * ir;  // the deviatoric correction is traceless
+  const float s = -2.0f * theta;
+  float chi = 0.0f;
+  if (COLL == 0) {
+    chi = (theta < 0.0f && s > c.J_min) ? fminf(1.0f, fmaxf(0.0f, c.gain * s)) : 0.0f;
+  }
+
+  // line 6: Newtonian stress tau = mu (grad u + grad u^T - 2/3 div u I), q = -kappa grad T
+  const float mir = mu * ir;
+  float tau[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+      tau[j][cc] = mir * (Xs[j][cc] + Xs[cc][j]) - (j == cc ? (2.0f / 3.0f) * mu * theta : 0.0f);
+
+  // line 7: full flux of eq. 2 in the equilibrium
+  float Phi[5][3];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    Phi[0][cc] = m[cc];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Phi[1 + j][cc] = m[j] * u[cc] + (j == cc ? p : 0.0f) - tau[j][cc];
+    const float tu = tau[cc][0] * u0 + tau[cc][1] * u1 + tau[cc][2] * u2;
+    Phi[4][cc] = H * u[cc] - tu - kap * gT[cc];
+  }
+
+  if constexpr (DIAG) {
+    const float wx = (X[2][1] - X[1][2]) * ir;  // curl from the antisymmetric part
+    const float wy = (X[0][2] - X[2][0]) * ir;
+    const float wz = (X[1][0] - X[0][1]) * ir;
+    d->ek = 0.5f * rf * k2;
+    d->eps_s = mu * (wx * wx + wy * wy + wz * wz);
+    d->eps_d = (4.0f / 3.0f) * mu * theta * theta;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) d->dq[k] = dq[k];
+  }
+
+  // lines 8-9: collision
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const float om = c.om[k == 0 ? 0 : (k == 4 ? 2 : 1)];
+    float* f = g + 7 * k;
+    const float q8 = 0.125f * dq[k];
+    if (COLL == 0) {
+      // regularized: J* = omega_h Phi + (1 - omega_h) J
+      const float oh = om - chi * (om - c.om_min);
+      const float jx = J[k][0] + oh * (Phi[k][0] - J[k][0]);
+      const float jy = J[k][1] + oh * (Phi[k][1] - J[k][1]);
+      const float jz = J[k][2] + oh * (Phi[k][2] - J[k][2]);
+      f[0] = 0.25f * dq[k];
+      f[1] = q8 + 0.5f * jx;
+      f[2] = q8 - 0.5f * jx;
+      f[3] = q8 + 0.5f * jy;
+      f[4] = q8 - 0.5f * jy;
+      f[5] = q8 + 0.5f * jz;
+      f[6] = q8 - 0.5f * jz;
+    } else {
+      // BGK: f <- f + omega (f_eq - f)
+      const float e0 = 0.25f * dq[k];
+      f[0] += om * (e0 - f[0]);
+      f[1] += om * ((q8 + 0.5f * Phi[k][0]) - f[1]);
+      f[2] += om * ((q8 - 0.5f * Phi[k][0]) - f[2]);
+      f[3] += om * ((q8 + 0.5f * Phi[k][1]) - f[3]);
+      f[4] += om * ((q8 - 0.5f * Phi[k][1]) - f[4]);
+      f[5] += om * ((q8 + 0.5f * Phi[k][2]) - f[5]);
+      f[6] += om * ((q8 - 0.5f * Phi[k][2]) - f[6]);
+    }
+  }
+  if constexpr (DIAG) {
+    bool bad = false;
+#pragma unroll
+    for (int s2 = 0; s2 < kPop; ++s2) bad |= !__builtin_isfinite(g[s2]);
+    d->nonfinite = bad ? 1.0f : 0.0f;
+  }
+}
+
+}  // namespace grlbm

@@ -1,0 +1,34 @@
+// grlbm_internal.h -- launchers shared between the kernels and the C ABI runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grlbm_device.hpp"
+
+namespace grlbm {
+
+struct StepLaunch {
+  void* F;           // population buffer
+  Grid g;
+  Coll c;
+  float* partials;   // per-block diagnostic partials (diag only)
+  int block;         // threads per block (multiple of 64, <= 1024)
+  int coll;          // 0 regularized with sensor, 1 BGK
+  bool odd;          // AA parity of this step
+  bool f16;          // FP16 storage
+  bool diag;         // fused diagnostics
+  bool nt;           // nontemporal loads and stores
+};
+
+hipError_t launch_step(const StepLaunch& L, hipStream_t s);
+int64_t step_blocks(const Grid& g, int block);
+hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s);
+hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const double* Q, int64_t N,
+                       hipStream_t s);
+hipError_t launch_gather(const void* F, bool f16, const Grid& g, const Coll& c, int64_t N, bool odd,
+                         int mode, float* out_f, double* out_q, hipStream_t s);
+hipError_t launch_scatter(void* F, bool f16, const Grid& g, int64_t N, bool odd, const float* in_f,
+                          hipStream_t s);
+hipError_t launch_copy(const void* a, void* b, int64_t bytes, hipStream_t s);
+
+}  // namespace grlbm

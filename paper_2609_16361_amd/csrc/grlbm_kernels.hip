@@ -1,0 +1,357 @@
+// grlbm_kernels.hip -- HIP kernels for gfx950 and their host-side launchers.
+//
+//   k_step      fused collide-and-stream update of one AA half step (even or odd
+//               parity): 35 loads, the collision of Algorithm 1 in registers, 35
+//               stores; optional fused diagnostics (wavefront shuffle + LDS
+//               reduction to one partial per block)
+//   k_finalize  deterministic reduction of the per-block partials into one record
+//   k_init      equilibrium populations from the conserved fields
+//   k_gather    parity-aware readout: canonical populations or conserved moments
+//   k_scatter   parity-aware write of canonical populations (checkpoint restore)
+//   k_copy      streaming copy used to measure achievable HBM bandwidth
+//
+// One lane owns one cell; a block covers `blockDim.x` consecutive cells of one
+// x-row, so every wave reads and writes 64 consecutive elements of each of the 35
+// arrays (coalesced).  The update is memory-bound (no contraction, no MFMA).
+#include <hip/hip_runtime.h>
+
+#include "grlbm_device.hpp"
+#include "grlbm_internal.h"
+
+namespace grlbm {
+
+// ----------------------------------------------------------------- block mapping
+struct CellPos {
+  int x, y, z;
+  bool active;
+};
+
+__device__ __forceinline__ CellPos block_cell(const Grid& g) {
+  const int bx = blockDim.x;
+  const int nxb = (g.nx + bx - 1) / bx;
+  const int b = blockIdx.x;
+  const int row = b / nxb;
+  CellPos p;
+  p.x = (b - row * nxb) * bx + threadIdx.x;
+  p.y = row % g.ny;
+  p.z = row / g.ny;
+  p.active = p.x < g.nx;
+  return p;
+}
+
+// -------------------------------------------------------- diagnostics reduction
+constexpr int kDiagVals = 9;  // ek, eps_s, eps_d, dq[5], nonfinite
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ void block_reduce_store(float vals[kDiagVals], float* __restrict__ out) {
+  __shared__ float sm[16][kDiagVals];  // up to 1024 threads = 16 waves
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < kDiagVals; ++j) vals[j] = wave_sum(vals[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < kDiagVals; ++j) sm[wave][j] = vals[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < kDiagVals) {
+    const int nw = (blockDim.x + 63) >> 6;
+    float s = 0.0f;
+    for (int w = 0; w < nw; ++w) s += sm[w][threadIdx.x];
+    out[(int64_t)blockIdx.x * kDiagVals + threadIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------ the update
+template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT>
+__global__ void __launch_bounds__(1024) k_step(T* __restrict__ F, Grid g, Coll c,
+                                                float* __restrict__ partials) {
+  const CellPos pos = block_cell(g);
+  float vals[kDiagVals];
+  if constexpr (DIAG) {
+#pragma unroll
+    for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
+  }
+  if (pos.active) {
+    const Nbr b = make_nbr(g, pos.x, pos.y, pos.z);
+    const int64_t S = g.S;
+    float f[kPop];
+    // stream half of AA: gather the post-stream populations of this cell
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      const T* Fk = F + (int64_t)(7 * k) * S;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) {
+        if constexpr (ODD) {
+          f[7 * k + i] = ld<T, NT>(Fk + odd_src<ZG>(g, b, i));
+        } else {
+          f[7 * k + i] = ld<T, NT>(Fk + (int64_t)i * S + b.n);
+        }
+      }
+    }
+    CellDiag d;
+    collide<COLL, DIAG>(f, c, &d);
+    if constexpr (DIAG) {
+      vals[0] = d.ek;
+      vals[1] = d.eps_s;
+      vals[2] = d.eps_d;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) vals[3 + k] = d.dq[k];
+      vals[8] = d.nonfinite;
+    }
+    // store half of AA
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      T* Fk = F + (int64_t)(7 * k) * S;
+      const float* fo = f + 7 * k;
+      if constexpr (!ODD) {
+        // own cell, opposite slot; on a zero-gradient face the ghost copy replaces
+        // the population that leaves the domain
+        st<T, NT>(Fk + b.n, fo[0]);
+        st<T, NT>(Fk + 1 * S + b.n, (ZG && b.lo_x) ? fo[1] : fo[2]);
+        st<T, NT>(Fk + 2 * S + b.n, (ZG && b.hi_x) ? fo[2] : fo[1]);
+        st<T, NT>(Fk + 3 * S + b.n, (ZG && b.lo_y) ? fo[3] : fo[4]);
+        st<T, NT>(Fk + 4 * S + b.n, (ZG && b.hi_y) ? fo[4] : fo[3]);
+        st<T, NT>(Fk + 5 * S + b.n, (ZG && b.lo_z) ? fo[5] : fo[6]);
+        st<T, NT>(Fk + 6 * S + b.n, (ZG && b.hi_z) ? fo[6] : fo[5]);
+      } else {
+        // slot i of the downstream cell x + c_i
+        st<T, NT>(Fk + b.n, fo[0]);
+        if (!(ZG && b.hi_x)) st<T, NT>(Fk + 1 * S + b.xp, fo[1]);
+        if (!(ZG && b.lo_x)) st<T, NT>(Fk + 2 * S + b.xm, fo[2]);
+        if (!(ZG && b.hi_y)) st<T, NT>(Fk + 3 * S + b.yp, fo[3]);
+        if (!(ZG && b.lo_y)) st<T, NT>(Fk + 4 * S + b.ym, fo[4]);
+        if (!(ZG && b.hi_z)) st<T, NT>(Fk + 5 * S + b.zp, fo[5]);
+        if (!(ZG && b.lo_z)) st<T, NT>(Fk + 6 * S + b.zm, fo[6]);
+        if constexpr (ZG) {
+          // ghost copy entering through a zero-gradient face
+          if (b.lo_x) st<T, NT>(Fk + 1 * S + b.n, fo[1]);
+          if (b.hi_x) st<T, NT>(Fk + 2 * S + b.n, fo[2]);
+          if (b.lo_y) st<T, NT>(Fk + 3 * S + b.n, fo[3]);
+          if (b.hi_y) st<T, NT>(Fk + 4 * S + b.n, fo[4]);
+          if (b.lo_z) st<T, NT>(Fk + 5 * S + b.n, fo[5]);
+          if (b.hi_z) st<T, NT>(Fk + 6 * S + b.n, fo[6]);
+        }
+      }
+    }
+  }
+  if constexpr (DIAG) block_reduce_store(vals, partials);
+}
+
+// One block of 1024 threads; partials[nblocks][9] -> rec[9].  Each thread sums a
+// fixed strided subset with compensated (Kahan) summation, then a fixed-order tree
+// in LDS; the result does not depend on timing.
+__global__ void __launch_bounds__(1024) k_finalize(const float* __restrict__ partials,
+                                                    int64_t nblocks, float* __restrict__ rec) {
+  __shared__ float sm[1024];
+  for (int j = 0; j < kDiagVals; ++j) {
+    float s = 0.0f, comp = 0.0f;
+    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
+      const float y = partials[b * kDiagVals + j] - comp;
+      const float t = s + y;
+      comp = (t - s) - y;
+      s = t;
+    }
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) rec[j] = sm[0];
+    __syncthreads();
+  }
+}
+
+// Equilibrium of Q with the advective flux: g_i = w_i (Q - Q_ref + 4 c_i . Phi_adv).
+template <typename T>
+__global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
+                                               const double* __restrict__ Q, int64_t N) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const float rho = (float)Q[n];
+  const float m[3] = {(float)Q[N + n], (float)Q[2 * N + n], (float)Q[3 * N + n]};
+  const float E = (float)Q[4 * N + n];
+  const float dq[5] = {(float)(Q[n] - (double)c.rho_ref), m[0], m[1], m[2],
+                       (float)(Q[4 * N + n] - (double)c.E_ref)};
+  const float rf = fmaxf(rho, c.rho_min);
+  const float ir = 1.0f / rf;
+  const float u[3] = {m[0] * ir, m[1] * ir, m[2] * ir};
+  const float k2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const float p = fmaxf(c.gm1 * (E - 0.5f * rf * k2), c.p_min);
+  float Phi[5][3];
+  for (int cc = 0; cc < 3; ++cc) {
+    Phi[0][cc] = m[cc];
+    for (int j = 0; j < 3; ++j) Phi[1 + j][cc] = m[j] * u[cc] + (j == cc ? p : 0.0f);
+    Phi[4][cc] = (E + p) * u[cc];
+  }
+  for (int k = 0; k < 5; ++k) {
+    T* Fk = F + (int64_t)(7 * k) * g.S + n;
+    const float q8 = 0.125f * dq[k];
+    Fk[0] = static_cast<T>(0.25f * dq[k]);
+    Fk[1 * g.S] = static_cast<T>(q8 + 0.5f * Phi[k][0]);
+    Fk[2 * g.S] = static_cast<T>(q8 - 0.5f * Phi[k][0]);
+    Fk[3 * g.S] = static_cast<T>(q8 + 0.5f * Phi[k][1]);
+    Fk[4 * g.S] = static_cast<T>(q8 - 0.5f * Phi[k][1]);
+    Fk[5 * g.S] = static_cast<T>(q8 + 0.5f * Phi[k][2]);
+    Fk[6 * g.S] = static_cast<T>(q8 - 0.5f * Phi[k][2]);
+  }
+}
+
+// Element offset of canonical f_i of field k at the lane's cell for a state of
+// the given parity.
+template <typename T>
+__device__ __forceinline__ int64_t canon_off(const Grid& g, const Nbr& b, int k, int i, bool odd) {
+  const int64_t base = (int64_t)(7 * k) * g.S;
+  if (!odd) return base + (int64_t)i * g.S + b.n;
+  return base + odd_src<true>(g, b, i);
+}
+
+__device__ __forceinline__ void cell_of(const Grid& g, int64_t n, int& x, int& y, int& z) {
+  x = (int)(n % g.nx);
+  const int64_t r = n / g.nx;
+  y = (int)(r % g.ny);
+  z = (int)(r / g.ny);
+}
+
+// mode 0: canonical populations -> out_f[35][N] (float)
+// mode 1: conserved moments Q_ref + sum_i g -> out_q[5][N] (double)
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather(const T* __restrict__ F, Grid g, Coll c,
+                                                 int64_t N, int odd, int mode,
+                                                 float* __restrict__ out_f,
+                                                 double* __restrict__ out_q) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  int x, y, z;
+  cell_of(g, n, x, y, z);
+  const Nbr b = make_nbr(g, x, y, z);
+  for (int k = 0; k < 5; ++k) {
+    float s = 0.0f;
+    for (int i = 0; i < kQ; ++i) {
+      const float v = static_cast<float>(F[canon_off<T>(g, b, k, i, odd != 0)]);
+      if (mode == 0) out_f[(int64_t)(7 * k + i) * N + n] = v;
+      s += v;
+    }
+    if (mode == 1) {
+      const double ref = (k == 0) ? (double)c.rho_ref : (k == 4 ? (double)c.E_ref : 0.0);
+      out_q[(int64_t)k * N + n] = ref + (double)s;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_scatter(T* __restrict__ F, Grid g, int64_t N, int odd,
+                                                  const float* __restrict__ in_f) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  int x, y, z;
+  cell_of(g, n, x, y, z);
+  const Nbr b = make_nbr(g, x, y, z);
+  for (int k = 0; k < 5; ++k)
+    for (int i = 0; i < kQ; ++i)
+      F[canon_off<T>(g, b, k, i, odd != 0)] = static_cast<T>(in_f[(int64_t)(7 * k + i) * N + n]);
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_copy(const v4f* __restrict__ a, v4f* __restrict__ b,
+                                               int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(&a[i]), &b[i]);
+}
+
+// ------------------------------------------------------------------ launchers
+template <bool ODD, int COLL, typename T, bool ZG, bool DIAG>
+static hipError_t launch_step_t(void* F, const Grid& g, const Coll& c, float* partials, int block,
+                                bool nt, hipStream_t s) {
+  const int nxb = (g.nx + block - 1) / block;
+  const int64_t blocks = (int64_t)nxb * g.ny * g.nz;
+  if (nt)
+    hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, true>), dim3((unsigned)blocks), dim3(block), 0,
+                       s, (T*)F, g, c, partials);
+  else
+    hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, false>), dim3((unsigned)blocks), dim3(block),
+                       0, s, (T*)F, g, c, partials);
+  return hipGetLastError();
+}
+
+template <typename T, bool ZG, bool DIAG>
+static hipError_t dispatch_odd_coll(const StepLaunch& L, hipStream_t s) {
+  const bool odd = L.odd;
+  if (L.coll == 0) {
+    return odd ? launch_step_t<true, 0, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, s)
+               : launch_step_t<false, 0, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, s);
+  }
+  return odd ? launch_step_t<true, 1, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, s)
+             : launch_step_t<false, 1, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, s);
+}
+
+template <typename T>
+static hipError_t dispatch_t(const StepLaunch& L, hipStream_t s) {
+  const bool zg = L.g.zg_x || L.g.zg_y || L.g.zg_z;
+  if (zg) return L.diag ? dispatch_odd_coll<T, true, true>(L, s) : dispatch_odd_coll<T, true, false>(L, s);
+  return L.diag ? dispatch_odd_coll<T, false, true>(L, s) : dispatch_odd_coll<T, false, false>(L, s);
+}
+
+hipError_t launch_step(const StepLaunch& L, hipStream_t s) {
+  if (L.f16) return dispatch_t<_Float16>(L, s);
+  return dispatch_t<float>(L, s);
+}
+
+int64_t step_blocks(const Grid& g, int block) {
+  return (int64_t)((g.nx + block - 1) / block) * g.ny * g.nz;
+}
+
+hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, partials, nblocks, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const double* Q, int64_t N,
+                       hipStream_t s) {
+  const unsigned blocks = (unsigned)((N + 255) / 256);
+  if (f16)
+    hipLaunchKernelGGL(k_init<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, c, Q, N);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, c, Q, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const void* F, bool f16, const Grid& g, const Coll& c, int64_t N, bool odd,
+                         int mode, float* out_f, double* out_q, hipStream_t s) {
+  const unsigned blocks = (unsigned)((N + 255) / 256);
+  if (f16)
+    hipLaunchKernelGGL(k_gather<_Float16>, dim3(blocks), dim3(256), 0, s, (const _Float16*)F, g, c, N,
+                       (int)odd, mode, out_f, out_q);
+  else
+    hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(256), 0, s, (const float*)F, g, c, N,
+                       (int)odd, mode, out_f, out_q);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(void* F, bool f16, const Grid& g, int64_t N, bool odd, const float* in_f,
+                          hipStream_t s) {
+  const unsigned blocks = (unsigned)((N + 255) / 256);
+  if (f16)
+    hipLaunchKernelGGL(k_scatter<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, N, (int)odd,
+                       in_f);
+  else
+    hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, N, (int)odd, in_f);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* a, void* b, int64_t bytes, hipStream_t s) {
+  const int64_t n4 = bytes / 16;
+  const unsigned blocks = 256 * 8 * 4;  // a few blocks per SIMD; grid-stride loop
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, (const v4f*)a, (v4f*)b, n4);
+  return hipGetLastError();
+}
+
+}  // namespace grlbm

@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* the HIP library loads and exports every function include/grlbm.h declares
+* the ctypes mirrors of lbm_params / lbm_diag match the C layout (checked with a
+  small C program compiled by gcc against the header)
+* lbm_state_bytes: 35 padded arrays; 140 B/cell FP32 and 70 B/cell FP16 (Sec. 4:
+  the five-field state of a 512^3 grid is about 19 GB)
+* parameter validation returns LBM_EINVAL with a message, before any device call
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2609_16361_amd import binding, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "grlbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(lbm_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    names = declared_functions()
+    assert len(names) >= 15, names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(binding.SIGNATURES), set(names) ^ set(binding.SIGNATURES)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "grlbm.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(lbm_params),"
+        " offsetof(lbm_params, gamma), offsetof(lbm_params, omega), offsetof(lbm_params, E_ref),"
+        " sizeof(lbm_diag), offsetof(lbm_diag, nonfinite)); return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
+    vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True,
+                                        check=True).stdout.split()))
+    P, D = binding.lbm_params, binding.lbm_diag
+    assert vals == [ctypes.sizeof(P), P.gamma.offset, P.omega.offset, P.E_ref.offset,
+                    ctypes.sizeof(D), D.nonfinite.offset]
+
+
+def test_state_bytes():
+    c = inputs.tgv(n=512, dims=(512, 512, 512))
+    p = binding.make_params(c.params)
+    n = 512 ** 3
+    assert binding.lbm_state_bytes(p) == 35 * 4 * n
+    assert abs(35 * 4 * n / 1e9 - 19) < 0.5          # "19 GB" at 512^3
+    p16 = binding.make_params(c.params, storage=binding.LBM_STORE_F16)
+    assert binding.lbm_state_bytes(p16) == 35 * 2 * n
+    small = binding.make_params(inputs.sod(n=100, ny=3, nz=1).params)
+    per = (300 + 63) // 64 * 64                      # arrays padded to 256 bytes
+    assert binding.lbm_state_bytes(small) == 35 * 4 * per
+    small.layout_pad = 1000
+    assert binding.lbm_state_bytes(small) == 35 * 4 * ((1300 + 63) // 64 * 64)
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda p: setattr(p, "nx", 0), "dims"),
+    (lambda p: p.bc.__setitem__(0, 7), "bc[0]"),
+    (lambda p: (p.bc.__setitem__(2, 1), setattr(p, "nz", 1)), "zero-gradient"),
+    (lambda p: p.omega.__setitem__(1, 2.5), "omega[1]"),
+    (lambda p: p.omega.__setitem__(4, 0.0), "omega[4]"),
+    (lambda p: p.omega.__setitem__(2, 1.5), "momentum"),
+    (lambda p: setattr(p, "gamma", 1.0), "gamma"),
+    (lambda p: setattr(p, "collision", 3), "collision"),
+    (lambda p: setattr(p, "storage", 9), "storage"),
+    (lambda p: setattr(p, "rho_min", 0.0), "rho_min"),
+    (lambda p: setattr(p, "layout_pad", -1), "layout_pad"),
+    (lambda p: setattr(p, "T_ref", float("nan")), "T_ref"),
+])
+def test_validation_rejects(mutate, needle):
+    p = binding.make_params(inputs.tgv(n=8, dims=(8, 8, 8)).params)
+    mutate(p)
+    assert binding.lbm_state_bytes(p) == 0
+    with pytest.raises(binding.LbmError) as e:
+        binding.lbm_create(p)
+    assert e.value.status == binding.LBM_EINVAL
+    assert needle in str(e.value)
+
+
+def test_null_arguments():
+    lib = binding.load()
+    assert lib.lbm_destroy(None) == 0
+    assert lib.lbm_step(None, 1, 0) == binding.LBM_EINVAL
+    assert "NULL" in binding.lbm_last_error()
+    cnt = ctypes.c_int32(5)
+    assert lib.lbm_diagnostics(None, None, 0, ctypes.byref(cnt)) == binding.LBM_EINVAL

@@ -1,0 +1,285 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP32 populations and arithmetic against FP64):
+  * one to three steps on tiny grids: every population of every cell, per field
+    max |g_gpu + w_i Q_ref - f_oracle| <= 2e-6 max|f_oracle| (a few FP32 roundings
+    of the moment sums and of the collision, nothing accumulates yet)
+  * smooth data after 100 steps: relative L2 of every conserved field <= 2e-5
+  * shocked cells (oracle sensor active at the end, dilated by 4 cells):
+    relative L2 <= 1e-3, where the sensor switch may flip on FP32 rounding
+Relative L2 of a field uses max(||Q_oracle||_2, rho_ref c_ref sqrt(N)) as the
+scale so that near-zero momentum components are compared on the flow's scale.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_16361_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+W = np.array([0.25] + [0.125] * 6)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def shift(params):
+    """w_i Q_ref,k for the 35 slots."""
+    qref = np.array([params["rho_ref"], 0, 0, 0, params["E_ref"]])
+    return (qref[:, None] * W[None, :]).reshape(35)
+
+
+def gpu_run(case, steps, storage=binding.LBM_STORE_F32, block=None, nt=None, diag_every=0,
+            split=None):
+    with binding.Solver(case.params, storage=storage, block=block, nontemporal=nt) as s:
+        s.init(case.Q0)
+        if split is None:
+            s.step(steps, diag_every)
+        else:
+            for n in split:
+                s.step(n, diag_every)
+        Q = s.moments()
+        f, st = s.populations()
+        d, status = s.diagnostics()
+    return Q, f, d, status
+
+
+def ora_run(case, steps, diag_every=0):
+    f0 = oracle.init(case.params, case.Q0)
+    f, d = oracle.run(case.params, f0, steps, diag_every)
+    return f, d
+
+
+def rel_l2(a, b, scale):
+    return np.linalg.norm((a - b).ravel()) / scale
+
+
+def field_scales(Q, params):
+    N = Q[0].size
+    c_ref = math.sqrt(params["gamma"] * (params["gamma"] - 1) * params["E_ref"] / params["rho_ref"])
+    floor = params["rho_ref"] * c_ref * math.sqrt(N)
+    return [max(np.linalg.norm(Q[k].ravel()), floor) for k in range(5)]
+
+
+TINY = [
+    ("4x4x4 periodic", (4, 4, 4), (0, 0, 0)),
+    ("3x5x7 periodic", (3, 5, 7), (0, 0, 0)),
+    ("5x3x4 zero-gradient x", (5, 3, 4), (1, 0, 0)),
+    ("6x2x3 zero-gradient all", (6, 2, 3), (1, 1, 1)),
+    ("70x3x2 zero-gradient x, ragged", (70, 3, 2), (1, 0, 0)),
+    ("2x2x2 zero-gradient all", (2, 2, 2), (1, 1, 1)),
+    ("9x1x1 periodic thin", (9, 1, 1), (0, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("coll", [inputs.RLB_SENSOR, inputs.BGK])
+@pytest.mark.parametrize("name,dims,bc", TINY)
+def test_tiny_grids_every_population(name, dims, bc, coll):
+    case = inputs.random_smooth(*dims, seed=sum(dims) + 7 * coll, amp=0.08, mach=1.2, bc=bc,
+                                collision=coll, J_min=1e-3, sensor_gain=20.0, omega_min=1.0)
+    sh = shift(case.params)
+    f_or = oracle.init(case.params, case.Q0)
+    for steps in (1, 2, 3):
+        say(f"tiny grid {name} coll={coll} steps={steps}")
+        f_or, _ = oracle.run(case.params, f_or, 1)
+        _, f_gpu, _, _ = gpu_run(case, steps)
+        g = f_gpu.reshape(35, -1).astype(np.float64) + sh[:, None]
+        for k in range(5):
+            ref = f_or[7 * k:7 * k + 7]
+            err = np.abs(g[7 * k:7 * k + 7] - ref).max() / np.abs(ref).max()
+            assert err <= 2e-6, (name, steps, k, err)
+
+
+def test_smooth_vortex_100_steps():
+    """Compressible Taylor-Green set-up (Mach 1.25, Re 1600, Sutherland, regularized
+    collision with sensor) on 32^3: every field within 2e-5 after 100 steps, and the
+    fused diagnostics against the oracle's."""
+    case = inputs.tgv(n=32, steps=100, diag_every=10)
+    say("tgv 32^3 100 steps")
+    Q, _, d, status = gpu_run(case, 100, diag_every=10)
+    assert status == binding.LBM_OK
+    f, dor = ora_run(case, 100, diag_every=10)
+    Qo = oracle.moments(case.params, f)
+    sc = field_scales(Qo, case.params)
+    for k in range(5):
+        e = rel_l2(Q[k], Qo[k], sc[k])
+        assert e <= 2e-5, (k, e)
+    assert len(d) == len(dor) == 10
+    for r, ro in zip(d, dor):
+        assert r["nonfinite"] == 0
+        assert r["Ek"] == pytest.approx(ro[0], rel=2e-5)
+        if r["step"] > 0:   # gradients are zero at the equilibrium start
+            assert r["eps_s"] == pytest.approx(ro[1], rel=2e-4)
+            assert r["eps_d"] == pytest.approx(ro[2], rel=2e-3, abs=1e-6 * ro[1])
+        N = case.cells
+        qref = [case.params["rho_ref"], 0, 0, 0, case.params["E_ref"]]
+        for k in range(5):
+            tot = ro[3 + k] - N * qref[k]
+            assert abs(r["dtotal"][k] - tot) <= 1e-5 * (abs(ro[3 + k]) + 1e-3 * N), k
+
+
+def test_sod_tube_config():
+    """Sod shock tube 256x4x4, 400 steps, zero-gradient ends (the parity workload):
+    uniform across the tube, relative L2 <= 1e-3 in shocked cells and overall."""
+    case = inputs.sod(n=256, ny=4, nz=4)
+    say("sod 256x4x4 400 steps")
+    Q, _, _, _ = gpu_run(case, case.steps)
+    assert np.array_equal(Q, np.broadcast_to(Q[:, :1, :1, :], Q.shape))
+    f, _ = ora_run(case, case.steps)
+    Qo = oracle.moments(case.params, f)
+    # shocked cells: oracle sensor active at the final state, dilated by 4 cells
+    fo = f.reshape(35, 4, 4, 256)[:, 0, 0, :]
+    chi = np.array([oracle.collide(case.params, fo[:, x])[1]["chi"] for x in range(256)])
+    mask = np.convolve((chi > 0).astype(float), np.ones(9), mode="same") > 0
+    assert mask.sum() > 0
+    sc = field_scales(Qo, case.params)
+    for k in (0, 1, 4):
+        a, b = Q[k][..., mask], Qo[k][..., mask]
+        e_sh = np.linalg.norm(a - b) / np.linalg.norm(b)
+        e_all = rel_l2(Q[k], Qo[k], sc[k])
+        assert e_sh <= 1e-3 and e_all <= 1e-3, (k, e_sh, e_all)
+
+
+def test_checkpoint_resume_and_determinism():
+    case = inputs.random_smooth(20, 9, 6, seed=5, amp=0.06, bc=(1, 0, 1))
+    say("checkpoint/resume 20x9x6")
+    Q1, f1, _, _ = gpu_run(case, 7)
+    Q2, f2, _, _ = gpu_run(case, 7, split=[3, 4])
+    assert np.array_equal(f1, f2) and np.array_equal(Q1, Q2)
+    with binding.Solver(case.params) as s:
+        s.init(case.Q0)
+        s.step(3)                     # odd parity: populations live in swapped slots
+        fa, st = s.populations()
+        assert st == 3
+        s.set_populations(fa, st)     # restore in place
+        fb, _ = s.populations()
+        assert np.array_equal(fa, fb)
+        s.step(4)
+        f3, _ = s.populations()
+    assert np.array_equal(f3, f1)
+    with binding.Solver(case.params) as s2:   # restore into a fresh context
+        s2.set_populations(fa, 3)
+        s2.step(4)
+        f4, _ = s2.populations()
+    assert np.array_equal(f4, f1)
+
+
+@pytest.mark.parametrize("block,nt", [(64, False), (128, True), (512, False), (1024, True)])
+def test_launch_shapes_bitwise(block, nt):
+    """Results do not depend on the block size or on nontemporal access; nx = 300
+    leaves a ragged last block for every block size."""
+    case = inputs.random_smooth(300, 3, 2, seed=2, amp=0.05, bc=(1, 0, 0))
+    say(f"launch shape block={block} nt={nt}")
+    _, fr, _, _ = gpu_run(case, 5)
+    _, fb, _, _ = gpu_run(case, 5, block=block, nt=nt)
+    assert np.array_equal(fr, fb)
+
+
+def test_periodic_conservation_gpu():
+    """Totals of the five fields on a periodic grid: FP32 rounding only.  (The
+    Mach 1.25 vortex is under-resolved on 24^3 and diverges after about 180 steps in
+    the oracle as well, so the check stops at 100.)"""
+    case = inputs.tgv(n=24, steps=100)
+    say("conservation 24^3 100 steps")
+    with binding.Solver(case.params) as s:
+        s.init(case.Q0)
+        t0 = s.moments().reshape(5, -1).sum(1)
+        s.step(100)
+        t1 = s.moments().reshape(5, -1).sum(1)
+    N = case.cells
+    assert abs(t1[0] - t0[0]) <= 1e-6 * N
+    assert abs(t1[4] - t0[4]) <= 1e-6 * abs(t0[4])
+    mscale = np.abs(case.Q0[1:4]).max()
+    for k in (1, 2, 3):
+        assert abs(t1[k] - t0[k]) <= 1e-6 * N * mscale
+
+
+def test_errors_and_empty_steps():
+    case = inputs.random_smooth(8, 4, 4, seed=1)
+    say("error paths")
+    with binding.Solver(case.params) as s:
+        with pytest.raises(binding.LbmError) as e:
+            s.step(1)
+        assert e.value.status == binding.LBM_ESTATE
+        s.init(case.Q0)
+        f0, _ = s.populations()
+        s.step(0)
+        f1, st = s.populations()
+        assert st == 0 and np.array_equal(f0, f1)
+        with pytest.raises(binding.LbmError):
+            s.step(-1)
+
+
+def test_nonfinite_state_reports_diverged():
+    case = inputs.random_smooth(8, 4, 4, seed=1)
+    Q = case.Q0.copy()
+    Q[4, 1, 2, 3] = np.nan
+    say("diverged state")
+    with binding.Solver(case.params) as s:
+        s.init(Q)
+        s.step(3, diag_every=1)
+        recs, status = s.diagnostics()
+    assert status == binding.LBM_EDIVERGED
+    assert recs[0]["nonfinite"] >= 1
+
+
+def test_full_size_sampled_cells_256():
+    """256^3 compressible Taylor-Green in the benchmark's launch configuration: after
+    one even and one odd step, sampled cells equal the oracle's collision of the
+    upstream neighbours' populations (periodic), per field within 2e-6."""
+    case = inputs.tgv(n=256)
+    sh = shift(case.params)
+    rng = np.random.default_rng(0)
+    n = 256
+    with binding.Solver(case.params) as s:
+        say("256^3 init")
+        s.init(case.Q0)
+        for steps in (1, 1, 1):  # check the update into odd, even and odd parity
+            f_pre, t = s.populations()
+            say(f"256^3 step {t} -> {t + 1}")
+            s.step(steps)
+            f_post, _ = s.populations()
+            pre = f_pre.reshape(35, n, n, n)
+            post = f_post.reshape(35, n, n, n)
+            cx = [0, 1, -1, 0, 0, 0, 0]
+            cy = [0, 0, 0, 1, -1, 0, 0]
+            cz = [0, 0, 0, 0, 0, 1, -1]
+            pts = [(0, 0, 0), (255, 255, 255), (0, 128, 255)] + \
+                [tuple(rng.integers(0, n, 3)) for _ in range(40)]
+            for (z, y, x) in pts:
+                expect = np.zeros(35)
+                for i in range(7):
+                    zs, ys, xs = (z - cz[i]) % n, (y - cy[i]) % n, (x - cx[i]) % n
+                    fin = pre[:, zs, ys, xs].astype(np.float64) + sh
+                    fo, _ = oracle.collide(case.params, fin)
+                    for k in range(5):
+                        expect[7 * k + i] = fo[7 * k + i]
+                got = post[:, z, y, x].astype(np.float64) + sh
+                for k in range(5):
+                    sl = slice(7 * k, 7 * k + 7)
+                    scale = np.abs(expect[sl]).max()
+                    assert np.abs(got[sl] - expect[sl]).max() <= 2e-6 * scale, (z, y, x, k)
+
+
+def test_torch_buffer_and_stream():
+    """Populations in a torch-owned device buffer, work on torch's current stream."""
+    import torch
+    case = inputs.random_smooth(40, 6, 5, seed=4, amp=0.05)
+    say("torch buffer/stream")
+    p = binding.make_params(case.params)
+    nbytes = binding.lbm_state_bytes(p)
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = binding.lbm_create_in(p, buf.data_ptr(), nbytes, stream)
+    try:
+        binding.lbm_init_fields(ctx, case.Q0)
+        binding.lbm_step(ctx, 6)
+        Q = binding.lbm_moments(ctx, (5, 6, 40))
+    finally:
+        binding.lbm_destroy(ctx)
+    Qr, _, _, _ = gpu_run(case, 6)
+    assert np.array_equal(Q, Qr)

@@ -259,8 +259,8 @@ def test_second_order_self_convergence():
 
 def test_beta_working_points():
     """eq. 6 with the unit mapping: beta = 2 nu_lat omega / c_s^2 is about 0.02 at the
-    compressible Taylor-Green working point (128^3) and 0.04 at 256^3."""
+    compressible Taylor-Green working point (128^3 at dt/dx = 0.1) and 0.04 at 256^3."""
     for n, expect in ((128, 0.0202), (256, 0.0407)):
-        p = inputs.tgv(n=n, dims=(2, 2, 2)).params
+        p = inputs.tgv(n=n, dims=(2, 2, 2), r=0.1).params
         beta = 2 * p["mu_ref"] * p["omega"][1] / 0.25
         assert beta == pytest.approx(expect, rel=5e-3)
