@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--layout-pad", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bw-probe", action="store_true")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
+                    help="only run the streaming-copy probe on BYTES bytes (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -76,6 +78,10 @@ def main():
     assert torch.cuda.is_available(), "no GPU visible"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_only:
+        gbs = binding.lbm_bw_probe(args.copy_only, 3)
+        print(json.dumps({"copy_bytes": args.copy_only, "copy_launches": 4, "copy_gbs": round(gbs, 1)}))
+        return
 
     case = inputs.tgv(n=args.n, diag_every=args.diag_every)
     cells = case.cells
@@ -129,7 +135,8 @@ def main():
                                f"Re 1600, regularized collision + sensor, diagnostics every "
                                f"{args.diag_every} steps",
                    "cells": cells, "steps": args.steps, "diag_every": args.diag_every,
-                   "block": args.block or 256, "nontemporal": bool(args.nontemporal),
+                   "block": args.block or 1024,
+                   "nontemporal": True if args.nontemporal is None else bool(args.nontemporal),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),

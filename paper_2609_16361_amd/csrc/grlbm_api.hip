@@ -40,6 +40,7 @@ lbm_status fail(lbm_status st, const char* fmt, ...) {
 
 constexpr int kDiagVals = 9;
 constexpr int32_t kRingCap = 1024;
+constexpr int64_t kLdsPerCU = 160 * 1024;  // gfx950
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -57,6 +58,7 @@ lbm_status validate(const lbm_params* p) {
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
   if (N > (int64_t)INT32_MAX / 2)
     return fail(LBM_EINVAL, "grid of %lld cells exceeds the 32-bit cell index range", (long long)N);
+
   if (p->collision != LBM_COLL_RLB_SENSOR && p->collision != LBM_COLL_BGK)
     return fail(LBM_EINVAL, "collision = %d is not an lbm_collision", p->collision);
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F16)
@@ -139,8 +141,9 @@ struct lbm_ctx {
   bool own_F = false;
   int64_t step = 0;
   bool ready = false;
-  int block = 256;
-  bool nt = false;
+  int block = 1024;
+  bool nt = true;
+  int lds = 0;
   float* partials = nullptr;
   int64_t partials_blocks = 0;
   float* ring = nullptr;
@@ -260,12 +263,17 @@ lbm_status lbm_create_in(const lbm_params* p, void* dev_buf, size_t bytes, void*
   return create_common(p, dev_buf, bytes, hip_stream, out);
 }
 
-lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t nontemporal) {
+lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t nontemporal, int32_t blocks_per_cu) {
   if (!c) return fail(LBM_EINVAL, "ctx is NULL");
   if (block < 64 || block > 1024 || block % 64 != 0)
     return fail(LBM_EINVAL, "block = %d must be a multiple of 64 in [64, 1024]", block);
+  if (blocks_per_cu < 0 || blocks_per_cu > 32)
+    return fail(LBM_EINVAL, "blocks_per_cu = %d outside [0, 32]", blocks_per_cu);
   c->block = block;
   c->nt = nontemporal != 0;
+  // reserve just over 1/(blocks_per_cu + 1) of the 160 KB LDS of a CU per block
+  c->lds = blocks_per_cu > 0 ? (int)(kLdsPerCU / (blocks_per_cu + 1)) + 256 : 0;
+  if (c->lds > 65536) c->lds = 65536;
   return LBM_OK;
 }
 
@@ -308,6 +316,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n, int32_t diag_every) {
   L.coll = c->p.collision;
   L.f16 = c->p.storage == LBM_STORE_F16;
   L.nt = c->nt;
+  L.lds = c->lds;
   L.partials = nullptr;
   if (diag_every > 0) {
     lbm_status st = ensure_partials(c);
@@ -435,7 +444,8 @@ lbm_status lbm_destroy(lbm_ctx* c) {
 }
 
 lbm_status lbm_bw_probe(size_t bytes, int32_t iters, double* gbps) {
-  if (!gbps || bytes < 16 || iters < 1) return fail(LBM_EINVAL, "bad bw_probe arguments");
+  if (!gbps || bytes < 16 || iters < 1 || bytes > ((size_t)1 << 40))
+    return fail(LBM_EINVAL, "bad bw_probe arguments");
   bytes = bytes / 16 * 16;
   void *a = nullptr, *b = nullptr;
   hipStream_t s = nullptr;

@@ -18,6 +18,7 @@ struct StepLaunch {
   bool f16;          // FP16 storage
   bool diag;         // fused diagnostics
   bool nt;           // nontemporal loads and stores
+  int lds;           // dynamic LDS bytes reserved per block (occupancy cap), 0 = none
 };
 
 hipError_t launch_step(const StepLaunch& L, hipStream_t s);

@@ -143,29 +143,27 @@ __global__ void __launch_bounds__(1024) k_step(T* __restrict__ F, Grid g, Coll c
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
-// One block of 1024 threads; partials[nblocks][9] -> rec[9].  Each thread sums a
-// fixed strided subset with compensated (Kahan) summation, then a fixed-order tree
-// in LDS; the result does not depend on timing.
+// One block of 1024 threads per value j: partials[nblocks][9] -> rec[j].  Each
+// thread sums a fixed strided subset with compensated (Kahan) summation, then a
+// fixed-order tree in LDS; the result does not depend on timing.
 __global__ void __launch_bounds__(1024) k_finalize(const float* __restrict__ partials,
                                                     int64_t nblocks, float* __restrict__ rec) {
   __shared__ float sm[1024];
-  for (int j = 0; j < kDiagVals; ++j) {
-    float s = 0.0f, comp = 0.0f;
-    for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
-      const float y = partials[b * kDiagVals + j] - comp;
-      const float t = s + y;
-      comp = (t - s) - y;
-      s = t;
-    }
-    sm[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) rec[j] = sm[0];
+  const int j = blockIdx.x;
+  float s = 0.0f, comp = 0.0f;
+  for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    const float y = partials[b * kDiagVals + j] - comp;
+    const float t = s + y;
+    comp = (t - s) - y;
+    s = t;
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
     __syncthreads();
   }
+  if (threadIdx.x == 0) rec[j] = sm[0];
 }
 
 // Equilibrium of Q with the advective flux: g_i = w_i (Q - Q_ref + 4 c_i . Phi_adv).
@@ -260,25 +258,28 @@ __global__ void __launch_bounds__(256) k_scatter(T* __restrict__ F, Grid g, int6
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// One 16-byte vector per lane, nontemporal in and out.
 __global__ void __launch_bounds__(256) k_copy(const v4f* __restrict__ a, v4f* __restrict__ b,
                                                int64_t n4) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
-       i += (int64_t)gridDim.x * blockDim.x)
-    __builtin_nontemporal_store(__builtin_nontemporal_load(&a[i]), &b[i]);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(&a[i]), &b[i]);
 }
 
 // ------------------------------------------------------------------ launchers
+// `lds` bytes of dynamic LDS are reserved per block (and never touched): with 160 KB
+// of LDS per CU this caps the resident blocks per CU, which the 35-stream access
+// pattern prefers low (about 16 waves per CU).
 template <bool ODD, int COLL, typename T, bool ZG, bool DIAG>
 static hipError_t launch_step_t(void* F, const Grid& g, const Coll& c, float* partials, int block,
-                                bool nt, hipStream_t s) {
+                                bool nt, int lds, hipStream_t s) {
   const int nxb = (g.nx + block - 1) / block;
   const int64_t blocks = (int64_t)nxb * g.ny * g.nz;
   if (nt)
-    hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, true>), dim3((unsigned)blocks), dim3(block), 0,
+    hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, true>), dim3((unsigned)blocks), dim3(block), lds,
                        s, (T*)F, g, c, partials);
   else
     hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, false>), dim3((unsigned)blocks), dim3(block),
-                       0, s, (T*)F, g, c, partials);
+                       lds, s, (T*)F, g, c, partials);
   return hipGetLastError();
 }
 
@@ -286,11 +287,11 @@ template <typename T, bool ZG, bool DIAG>
 static hipError_t dispatch_odd_coll(const StepLaunch& L, hipStream_t s) {
   const bool odd = L.odd;
   if (L.coll == 0) {
-    return odd ? launch_step_t<true, 0, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, s)
-               : launch_step_t<false, 0, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, s);
+    return odd ? launch_step_t<true, 0, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, L.lds, s)
+               : launch_step_t<false, 0, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, L.lds, s);
   }
-  return odd ? launch_step_t<true, 1, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, s)
-             : launch_step_t<false, 1, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, s);
+  return odd ? launch_step_t<true, 1, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, L.lds, s)
+             : launch_step_t<false, 1, T, ZG, DIAG>(L.F, L.g, L.c, L.partials, L.block, L.nt, L.lds, s);
 }
 
 template <typename T>
@@ -310,7 +311,7 @@ int64_t step_blocks(const Grid& g, int block) {
 }
 
 hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, partials, nblocks, rec);
+  hipLaunchKernelGGL(k_finalize, dim3(kDiagVals), dim3(1024), 0, s, partials, nblocks, rec);
   return hipGetLastError();
 }
 
@@ -349,7 +350,7 @@ hipError_t launch_scatter(void* F, bool f16, const Grid& g, int64_t N, bool odd,
 
 hipError_t launch_copy(const void* a, void* b, int64_t bytes, hipStream_t s) {
   const int64_t n4 = bytes / 16;
-  const unsigned blocks = 256 * 8 * 4;  // a few blocks per SIMD; grid-stride loop
+  const unsigned blocks = (unsigned)((n4 + 255) / 256);
   hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, (const v4f*)a, (v4f*)b, n4);
   return hipGetLastError();
 }

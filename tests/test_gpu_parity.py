@@ -168,14 +168,18 @@ def test_checkpoint_resume_and_determinism():
     assert np.array_equal(f4, f1)
 
 
-@pytest.mark.parametrize("block,nt", [(64, False), (128, True), (512, False), (1024, True)])
-def test_launch_shapes_bitwise(block, nt):
-    """Results do not depend on the block size or on nontemporal access; nx = 300
-    leaves a ragged last block for every block size."""
+@pytest.mark.parametrize("block,nt,bpc", [(64, False, 0), (128, True, 8), (256, False, 3),
+                                          (512, True, 2), (1024, False, 1)])
+def test_launch_shapes_bitwise(block, nt, bpc):
+    """Results do not depend on the block size, nontemporal access or the occupancy
+    cap; nx = 300 leaves a ragged last block for every block size."""
     case = inputs.random_smooth(300, 3, 2, seed=2, amp=0.05, bc=(1, 0, 0))
-    say(f"launch shape block={block} nt={nt}")
-    _, fr, _, _ = gpu_run(case, 5)
-    _, fb, _, _ = gpu_run(case, 5, block=block, nt=nt)
+    say(f"launch shape block={block} nt={nt} blocks_per_cu={bpc}")
+    _, fr, _, _ = gpu_run(case, 5, diag_every=2)
+    with binding.Solver(case.params, block=block, nontemporal=nt, blocks_per_cu=bpc) as s:
+        s.init(case.Q0)
+        s.step(5, 2)
+        fb, _ = s.populations()
     assert np.array_equal(fr, fb)
 
 
