@@ -49,6 +49,20 @@ def cpu_baseline(target_s=10.0):
                       f"after 1 warm-up step, {dt:.1f} s"}
 
 
+def measured_traffic():
+    """HBM bytes per launch of the collide-and-stream kernel from the committed
+    FETCH_SIZE/WRITE_SIZE counter runs, or None if the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_step_tgv256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for p in rec["sources"]:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,7 +154,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
                      "bytes_per_lup": BYTES_PER_LUP_F32, "avg_launch_ms": round(avg_launch_ms, 5)},
         "host_wall_s": round(t_host, 3),
         "copy_bw_gbs": None if bw is None else round(bw, 1),
