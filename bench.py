@@ -49,6 +49,79 @@ def cpu_baseline(target_s=10.0):
                       f"after 1 warm-up step, {dt:.1f} s"}
 
 
+def becker_linf(case, Q):
+    """L-inf error of the density profile (row y = z = 0) against the closed-form
+    Becker shock, relative to the density jump, after the best sub-cell shift of the
+    exact profile (the discrete shock may settle a fraction of a cell away)."""
+    import numpy as np
+    from paper_2609_16361_amd import inputs
+    m = case.meta
+    rho = Q[0, 0, 0, :]
+    best = None
+    for sh in np.linspace(-2.0, 2.0, 81):
+        re = inputs.becker_profile(m["x"], m["mach"], m["mu"], m["x_shock"] + sh, m["gamma"], 1.0,
+                                   m["c1"])[0]
+        e = np.abs(rho - re).max() / (re.max() - re.min())
+        if best is None or e < best[0]:
+            best = (e, sh)
+    return best
+
+
+def bench_batch(count=64, steps=5000, seed=0, stream=None):
+    """Batched Becker shocks (seeded lengths 512-8192 x 4 x 4, Mach 1.5-5, FP32,
+    regularized collision with sensor): autotuned persistent kernel + graphs, against
+    the same solves run one after another in single contexts."""
+    import numpy as np
+    import torch
+    from paper_2609_16361_amd import binding, inputs
+    cases = inputs.becker_batch(count, seed=seed)
+    cells = sum(c.cells for c in cases)
+    nbytes = sum(binding.lbm_state_bytes(binding.make_params(c.params)) for c in cases)
+    out = {"instances": count, "steps": steps, "cells": cells, "seed": seed}
+    t_wall = time.perf_counter()
+    with binding.Batch(int(nbytes * 1.05) + (64 << 20), max_instances=count, graph_steps=50,
+                       stream=stream.cuda_stream) as b:
+        ids = [b.add(c.params, c.Q0, steps) for c in cases]
+        best, best_us, tried = b.autotune(trial_steps=50)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.run(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_batch = e0.elapsed_time(e1) * 1e-3
+        errs = []
+        for i, c in zip(ids, cases):
+            done, fin = b.query(i)
+            assert fin and done == steps
+            errs.append(becker_linf(c, b.moments(i))[0])
+    t_wall = time.perf_counter() - t_wall
+    out["batched"] = {"solves_per_s": count / t_batch, "run_s": t_batch, "glups": cells * steps / t_batch / 1e9,
+                      "hbm_frac": 280.0 * cells * steps / t_batch / 1e9 / HBM_PEAK_GBS,
+                      "tuning": best, "tuned_us_per_step": best_us, "candidates": len(tried),
+                      "wall_s_incl_init_readout": t_wall}
+    out["linf_rel_error"] = {"median": float(np.median(errs)), "max": float(np.max(errs)),
+                             "mach_of_max": float(cases[int(np.argmax(errs))].meta["mach"])}
+    # the same solves one at a time, plain FP32 single contexts
+    t_seq = 0.0
+    t_wall = time.perf_counter()
+    for c in cases:
+        with binding.Solver(c.params, stream=stream.cuda_stream) as s:
+            s.init(c.Q0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_seq += e0.elapsed_time(e1) * 1e-3
+    t_wall = time.perf_counter() - t_wall
+    out["sequential"] = {"solves_per_s": count / t_seq, "run_s": t_seq, "glups": cells * steps / t_seq / 1e9,
+                         "wall_s_incl_init_readout": t_wall}
+    out["speedup"] = t_seq / t_batch
+    return out
+
+
 def measured_traffic():
     """HBM bytes per launch of the collide-and-stream kernel from the committed
     FETCH_SIZE/WRITE_SIZE counter runs, or None if the kernel sources changed since."""
@@ -75,6 +148,8 @@ def main():
     ap.add_argument("--layout-pad", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bw-probe", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched Becker workload")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched Becker workload")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run the streaming-copy probe on BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -95,6 +170,9 @@ def main():
     if args.copy_only:
         gbs = binding.lbm_bw_probe(args.copy_only, 3)
         print(json.dumps({"copy_bytes": args.copy_only, "copy_launches": 4, "copy_gbs": round(gbs, 1)}))
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": bench_batch(stream=stream)}), flush=True)
         return
 
     case = inputs.tgv(n=args.n, diag_every=args.diag_every)
@@ -161,6 +239,8 @@ def main():
         "diag_records": len(recs),
         "Ek_last": recs[-1]["Ek"] / cells if recs else None,
     }
+    if not args.no_batch:
+        out["batch"] = bench_batch(stream=stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -164,6 +164,86 @@ lbm_status lbm_get_step(lbm_ctx* ctx, int64_t* step);
 /* Release the context (waits for its stream first).  NULL is a no-op. */
 lbm_status lbm_destroy(lbm_ctx* ctx);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent instances (different sizes, boundaries, parameters, storage
+ * types and start times) advanced together: one persistent kernel per (collision,
+ * storage) group walks a tile work-list (a tile is one block-width chunk of one
+ * x-row of one instance), and time loops of `graph_steps` steps replay one captured
+ * HIP graph.  Every instance keeps its own step count: it is at its step 0 when
+ * added, advances with each lbm_batch_run step until it has made the number of
+ * steps it was added with, then stays frozen until removed.  Results are bitwise
+ * those of the same instance run alone in a context (lbm_create/lbm_step).  All
+ * calls use the batch's stream; calls that touch host memory synchronise it. */
+typedef struct lbm_batch lbm_batch; /* opaque */
+
+typedef struct {
+  int32_t block;          /* threads per block = tile width in cells (64..1024)   */
+  int32_t nontemporal;    /* nontemporal loads and stores                          */
+  int32_t blocks_per_cu;  /* occupancy cap enforced by an LDS reservation (0 = off) */
+  int32_t grid;           /* persistent grid size in blocks                        */
+} lbm_batch_tuning;
+
+typedef struct {
+  int64_t clock;               /* steps run so far by the batch                    */
+  size_t arena_bytes, arena_free_bytes, arena_largest_free;
+  int32_t live_instances;      /* added and not removed                            */
+  int32_t active_instances;    /* live and not yet finished                        */
+  int64_t active_cells;
+  lbm_batch_tuning tuning;
+  int32_t graph_steps;
+} lbm_batch_stats;
+
+/* Create a batch: one device arena of arena_bytes for the populations of all its
+ * instances, room for max_instances descriptors and max_tiles tiles per group, and
+ * time loops captured in graphs of graph_steps steps (1..4096; 1 = no graph).
+ * hip_stream as for lbm_create.  EINVAL on bad sizes, ENOMEM if the arena does not
+ * fit. */
+lbm_status lbm_batch_create(size_t arena_bytes, int32_t max_instances, int32_t max_tiles,
+                            int32_t graph_steps, void* hip_stream, lbm_batch** out);
+
+/* Add an instance (params as for lbm_create, validated the same way) initialised
+ * like lbm_init_fields from the host array Q [5][nz][ny][nx], to make `steps`
+ * steps.  *id receives its handle.  ENOMEM when the arena has no free run large
+ * enough, the descriptor table is full or its tiles exceed max_tiles. */
+lbm_status lbm_batch_add(lbm_batch* b, const lbm_params* p, const double* Q, int64_t steps,
+                         int32_t* id);
+
+/* Advance the batch by n >= 0 steps (asynchronous). */
+lbm_status lbm_batch_run(lbm_batch* b, int64_t n);
+
+/* Steps an instance has completed and whether it has finished (both may be NULL). */
+lbm_status lbm_batch_query(lbm_batch* b, int32_t id, int64_t* done_steps, int32_t* finished);
+
+/* Conserved fields of an instance, as lbm_moments (synchronises). */
+lbm_status lbm_batch_moments(lbm_batch* b, int32_t id, double* Q_out);
+
+/* Canonical populations of an instance and its completed steps, as
+ * lbm_get_populations (synchronises). */
+lbm_status lbm_batch_populations(lbm_batch* b, int32_t id, float* f_out, int64_t* step);
+
+/* Release an instance's arena space and descriptor (synchronises first). */
+lbm_status lbm_batch_remove(lbm_batch* b, int32_t id);
+
+/* Occupancy and tuning summary. */
+lbm_status lbm_batch_info(lbm_batch* b, lbm_batch_stats* out);
+
+/* Set the launch shape (invalidates the captured graph).  EINVAL on bad values,
+ * ENOMEM if the tile width needs more tiles than the capacity. */
+lbm_status lbm_batch_set_tuning(lbm_batch* b, const lbm_batch_tuning* t);
+
+/* Time every candidate launch shape on the batch's live instances for trial_steps
+ * steps each, restoring the populations and the clock after each trial (results do
+ * not depend on the shape), and keep the fastest.  best/best_us receive it and its
+ * time per step; up to max_tried (shape, time) pairs go to tried/tried_us (may be
+ * NULL), their number to *ntried.  Needs device memory for one copy of the used
+ * arena. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_batch_tuning* best,
+                              float* best_us, lbm_batch_tuning* tried, float* tried_us,
+                              int32_t max_tried, int32_t* ntried);
+
+/* Release the batch (waits for its stream).  NULL is a no-op. */
+lbm_status lbm_batch_destroy(lbm_batch* b);
+
 /* Achievable HBM bandwidth: a streaming copy of `bytes` bytes (read + write)
  * repeated `iters` times on a private stream; *gbps receives (2 * bytes) / time of
  * the fastest repetition in GB/s.  Allocates and frees its own buffers. */

@@ -49,6 +49,23 @@ class lbm_diag(ctypes.Structure):
     ]
 
 
+class lbm_batch_tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(block=self.block, nontemporal=self.nontemporal,
+                    blocks_per_cu=self.blocks_per_cu, grid=self.grid)
+
+
+class lbm_batch_stats(ctypes.Structure):
+    _fields_ = [("clock", ctypes.c_int64), ("arena_bytes", ctypes.c_size_t),
+                ("arena_free_bytes", ctypes.c_size_t), ("arena_largest_free", ctypes.c_size_t),
+                ("live_instances", ctypes.c_int32), ("active_instances", ctypes.c_int32),
+                ("active_cells", ctypes.c_int64), ("tuning", lbm_batch_tuning),
+                ("graph_steps", ctypes.c_int32)]
+
+
 class LbmError(RuntimeError):
     def __init__(self, status, where, msg):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
@@ -77,6 +94,21 @@ SIGNATURES = {
     "lbm_destroy": (ctypes.c_int, [_vp]),
     "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_double)]),
     "lbm_last_error": (ctypes.c_char_p, []),
+    "lbm_batch_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        _vp, _P(_vp)]),
+    "lbm_batch_add": (ctypes.c_int, [_vp, _P(lbm_params), _P(ctypes.c_double), ctypes.c_int64,
+                                     _P(ctypes.c_int32)]),
+    "lbm_batch_run": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "lbm_batch_query": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_int32)]),
+    "lbm_batch_moments": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_double)]),
+    "lbm_batch_populations": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_float), _P(ctypes.c_int64)]),
+    "lbm_batch_remove": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "lbm_batch_info": (ctypes.c_int, [_vp, _P(lbm_batch_stats)]),
+    "lbm_batch_set_tuning": (ctypes.c_int, [_vp, _P(lbm_batch_tuning)]),
+    "lbm_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _P(lbm_batch_tuning), _P(ctypes.c_float),
+                                          _P(lbm_batch_tuning), _P(ctypes.c_float), ctypes.c_int32,
+                                          _P(ctypes.c_int32)]),
+    "lbm_batch_destroy": (ctypes.c_int, [_vp]),
 }
 
 
@@ -275,6 +307,140 @@ class Solver:
         if self.ctx:
             lbm_destroy(self.ctx)
             self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------- batches
+def lbm_batch_create(arena_bytes: int, max_instances: int, max_tiles: int, graph_steps: int = 16,
+                     stream: int | None = None) -> int:
+    h = _vp()
+    _check(load().lbm_batch_create(int(arena_bytes), int(max_instances), int(max_tiles),
+                                   int(graph_steps), stream, ctypes.byref(h)), "lbm_batch_create")
+    return h.value
+
+
+def lbm_batch_add(batch: int, params: lbm_params, Q: np.ndarray, steps: int) -> int:
+    q = np.ascontiguousarray(Q, dtype=np.float64)
+    i = ctypes.c_int32(-1)
+    _check(load().lbm_batch_add(batch, ctypes.byref(params), q.ctypes.data_as(_P(ctypes.c_double)),
+                                int(steps), ctypes.byref(i)), "lbm_batch_add")
+    return i.value
+
+
+def lbm_batch_run(batch: int, n: int) -> None:
+    _check(load().lbm_batch_run(batch, int(n)), "lbm_batch_run")
+
+
+def lbm_batch_query(batch: int, inst: int):
+    d = ctypes.c_int64(0)
+    f = ctypes.c_int32(0)
+    _check(load().lbm_batch_query(batch, int(inst), ctypes.byref(d), ctypes.byref(f)), "lbm_batch_query")
+    return d.value, bool(f.value)
+
+
+def lbm_batch_moments(batch: int, inst: int, shape) -> np.ndarray:
+    out = np.empty((5,) + tuple(shape), dtype=np.float64)
+    _check(load().lbm_batch_moments(batch, int(inst), out.ctypes.data_as(_P(ctypes.c_double))),
+           "lbm_batch_moments")
+    return out
+
+
+def lbm_batch_populations(batch: int, inst: int, shape):
+    f = np.empty((35,) + tuple(shape), dtype=np.float32)
+    s = ctypes.c_int64(0)
+    _check(load().lbm_batch_populations(batch, int(inst), f.ctypes.data_as(_P(ctypes.c_float)),
+                                        ctypes.byref(s)), "lbm_batch_populations")
+    return f, s.value
+
+
+def lbm_batch_remove(batch: int, inst: int) -> None:
+    _check(load().lbm_batch_remove(batch, int(inst)), "lbm_batch_remove")
+
+
+def lbm_batch_info(batch: int) -> dict:
+    s = lbm_batch_stats()
+    _check(load().lbm_batch_info(batch, ctypes.byref(s)), "lbm_batch_info")
+    return dict(clock=s.clock, arena_bytes=s.arena_bytes, arena_free_bytes=s.arena_free_bytes,
+                arena_largest_free=s.arena_largest_free, live_instances=s.live_instances,
+                active_instances=s.active_instances, active_cells=s.active_cells,
+                tuning=s.tuning.as_dict(), graph_steps=s.graph_steps)
+
+
+def lbm_batch_set_tuning(batch: int, block: int, nontemporal: bool, blocks_per_cu: int, grid: int) -> None:
+    t = lbm_batch_tuning(int(block), int(bool(nontemporal)), int(blocks_per_cu), int(grid))
+    _check(load().lbm_batch_set_tuning(batch, ctypes.byref(t)), "lbm_batch_set_tuning")
+
+
+def lbm_batch_autotune(batch: int, trial_steps: int = 20, max_tried: int = 64):
+    """Returns (best tuning dict, best us/step, [(tuning dict, us/step), ...])."""
+    best = lbm_batch_tuning()
+    bus = ctypes.c_float(0)
+    tried = (lbm_batch_tuning * max_tried)()
+    tus = (ctypes.c_float * max_tried)()
+    n = ctypes.c_int32(0)
+    _check(load().lbm_batch_autotune(batch, int(trial_steps), ctypes.byref(best), ctypes.byref(bus),
+                                     tried, tus, int(max_tried), ctypes.byref(n)), "lbm_batch_autotune")
+    return best.as_dict(), bus.value, [(tried[i].as_dict(), tus[i]) for i in range(n.value)]
+
+
+def lbm_batch_destroy(batch: int) -> None:
+    _check(load().lbm_batch_destroy(batch), "lbm_batch_destroy")
+
+
+class Batch:
+    """Owns one lbm_batch; instances are added from parameter dicts."""
+
+    def __init__(self, arena_bytes: int, max_instances: int = 1024, max_tiles: int = 1 << 20,
+                 graph_steps: int = 16, stream: int | None = None):
+        self.h = lbm_batch_create(arena_bytes, max_instances, max_tiles, graph_steps, stream)
+        self.shapes = {}
+
+    def add(self, params: dict, Q, steps: int, storage: int | None = None) -> int:
+        p = make_params(params, storage=storage)
+        i = lbm_batch_add(self.h, p, np.asarray(Q, dtype=np.float64), steps)
+        self.shapes[i] = (p.nz, p.ny, p.nx)
+        return i
+
+    def run(self, n: int) -> None:
+        lbm_batch_run(self.h, n)
+
+    def query(self, i: int):
+        return lbm_batch_query(self.h, i)
+
+    def moments(self, i: int):
+        return lbm_batch_moments(self.h, i, self.shapes[i])
+
+    def populations(self, i: int):
+        return lbm_batch_populations(self.h, i, self.shapes[i])
+
+    def remove(self, i: int) -> None:
+        lbm_batch_remove(self.h, i)
+        self.shapes.pop(i, None)
+
+    def info(self) -> dict:
+        return lbm_batch_info(self.h)
+
+    def autotune(self, trial_steps: int = 20):
+        return lbm_batch_autotune(self.h, trial_steps)
+
+    def set_tuning(self, block, nontemporal, blocks_per_cu, grid):
+        lbm_batch_set_tuning(self.h, block, nontemporal, blocks_per_cu, grid)
+
+    def close(self):
+        if self.h:
+            lbm_batch_destroy(self.h)
+            self.h = None
 
     def __enter__(self):
         return self

@@ -16,8 +16,9 @@
 
 using grlbm::Coll;
 using grlbm::Grid;
+using grlbm::fail;
 
-namespace {
+namespace grlbm {
 
 thread_local std::string g_err;
 
@@ -31,18 +32,7 @@ lbm_status fail(lbm_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));         \
-  } while (0)
-
-constexpr int kDiagVals = 9;
-constexpr int32_t kRingCap = 1024;
-constexpr int64_t kLdsPerCU = 160 * 1024;  // gfx950
-
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 lbm_status validate(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
@@ -126,6 +116,32 @@ Coll make_coll(const lbm_params* p) {
   return c;
 }
 
+Grid make_grid(const lbm_params* p) {
+  Grid g;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.nz = p->nz;
+  g.zg_x = p->bc[0] == LBM_BC_ZERO_GRADIENT;
+  g.zg_y = p->bc[1] == LBM_BC_ZERO_GRADIENT;
+  g.zg_z = p->bc[2] == LBM_BC_ZERO_GRADIENT;
+  g.S = slot_stride(p);
+  return g;
+}
+
+}  // namespace grlbm
+
+using grlbm::make_coll;
+using grlbm::make_grid;
+using grlbm::slot_stride;
+using grlbm::state_bytes;
+using grlbm::validate;
+
+namespace {
+
+constexpr int kDiagVals = 9;
+constexpr int32_t kRingCap = 1024;
+constexpr int64_t kLdsPerCU = 160 * 1024;  // gfx950
+
 }  // namespace
 
 struct lbm_ctx {
@@ -196,13 +212,7 @@ lbm_status create_common(const lbm_params* p, void* buf, size_t bytes, void* str
   if (!c) return fail(LBM_ENOMEM, "host allocation of the context failed");
   c->p = *p;
   c->N = (int64_t)p->nx * p->ny * p->nz;
-  c->g.nx = p->nx;
-  c->g.ny = p->ny;
-  c->g.nz = p->nz;
-  c->g.zg_x = p->bc[0] == LBM_BC_ZERO_GRADIENT;
-  c->g.zg_y = p->bc[1] == LBM_BC_ZERO_GRADIENT;
-  c->g.zg_z = p->bc[2] == LBM_BC_ZERO_GRADIENT;
-  c->g.S = slot_stride(p);
+  c->g = make_grid(p);
   c->c = make_coll(p);
   c->F_bytes = state_bytes(p);
   auto bail = [&](lbm_status s) {
@@ -488,6 +498,6 @@ done:
   return st;
 }
 
-const char* lbm_last_error(void) { return g_err.c_str(); }
+const char* lbm_last_error(void) { return grlbm::g_err.c_str(); }
 
 }  // extern "C"

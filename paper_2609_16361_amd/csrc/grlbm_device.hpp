@@ -314,4 +314,74 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
   }
 }
 
+// ----------------------------------------------------------------- one cell
+// One cell's AA half step: gather the post-stream populations, run the collision of
+// Algorithm 1 in registers, scatter the post-collision ones.  F points at slot 0 of
+// the instance's arrays.  With DIAG, vals[9] receives the cell's diagnostic densities.
+template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT>
+__device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, const Coll& c, int x,
+                                            int y, int z, float* vals) {
+  const Nbr b = make_nbr(g, x, y, z);
+  const int64_t S = g.S;
+  float f[kPop];
+  // stream half of AA: gather the post-stream populations of this cell
+#pragma unroll
+  for (int k = 0; k < kFields; ++k) {
+    const T* Fk = F + (int64_t)(7 * k) * S;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      if constexpr (ODD) {
+        f[7 * k + i] = ld<T, NT>(Fk + odd_src<ZG>(g, b, i));
+      } else {
+        f[7 * k + i] = ld<T, NT>(Fk + (int64_t)i * S + b.n);
+      }
+    }
+  }
+  CellDiag d;
+  collide<COLL, DIAG>(f, c, &d);
+  if constexpr (DIAG) {
+    vals[0] = d.ek;
+    vals[1] = d.eps_s;
+    vals[2] = d.eps_d;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) vals[3 + k] = d.dq[k];
+    vals[8] = d.nonfinite;
+  }
+  // store half of AA
+#pragma unroll
+  for (int k = 0; k < kFields; ++k) {
+    T* Fk = F + (int64_t)(7 * k) * S;
+    const float* fo = f + 7 * k;
+    if constexpr (!ODD) {
+      // own cell, opposite slot; on a zero-gradient face the ghost copy replaces
+      // the population that leaves the domain
+      st<T, NT>(Fk + b.n, fo[0]);
+      st<T, NT>(Fk + 1 * S + b.n, (ZG && b.lo_x) ? fo[1] : fo[2]);
+      st<T, NT>(Fk + 2 * S + b.n, (ZG && b.hi_x) ? fo[2] : fo[1]);
+      st<T, NT>(Fk + 3 * S + b.n, (ZG && b.lo_y) ? fo[3] : fo[4]);
+      st<T, NT>(Fk + 4 * S + b.n, (ZG && b.hi_y) ? fo[4] : fo[3]);
+      st<T, NT>(Fk + 5 * S + b.n, (ZG && b.lo_z) ? fo[5] : fo[6]);
+      st<T, NT>(Fk + 6 * S + b.n, (ZG && b.hi_z) ? fo[6] : fo[5]);
+    } else {
+      // slot i of the downstream cell x + c_i
+      st<T, NT>(Fk + b.n, fo[0]);
+      if (!(ZG && b.hi_x)) st<T, NT>(Fk + 1 * S + b.xp, fo[1]);
+      if (!(ZG && b.lo_x)) st<T, NT>(Fk + 2 * S + b.xm, fo[2]);
+      if (!(ZG && b.hi_y)) st<T, NT>(Fk + 3 * S + b.yp, fo[3]);
+      if (!(ZG && b.lo_y)) st<T, NT>(Fk + 4 * S + b.ym, fo[4]);
+      if (!(ZG && b.hi_z)) st<T, NT>(Fk + 5 * S + b.zp, fo[5]);
+      if (!(ZG && b.lo_z)) st<T, NT>(Fk + 6 * S + b.zm, fo[6]);
+      if constexpr (ZG) {
+        // ghost copy entering through a zero-gradient face
+        if (b.lo_x) st<T, NT>(Fk + 1 * S + b.n, fo[1]);
+        if (b.hi_x) st<T, NT>(Fk + 2 * S + b.n, fo[2]);
+        if (b.lo_y) st<T, NT>(Fk + 3 * S + b.n, fo[3]);
+        if (b.hi_y) st<T, NT>(Fk + 4 * S + b.n, fo[4]);
+        if (b.lo_z) st<T, NT>(Fk + 5 * S + b.n, fo[5]);
+        if (b.hi_z) st<T, NT>(Fk + 6 * S + b.n, fo[6]);
+      }
+    }
+  }
+}
+
 }  // namespace grlbm

@@ -3,9 +3,25 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/grlbm.h"
 #include "grlbm_device.hpp"
 
+// Failure with a message for lbm_last_error (returns st).
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return grlbm::fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
 namespace grlbm {
+
+lbm_status fail(lbm_status st, const char* fmt, ...);
+lbm_status validate(const lbm_params* p);
+int64_t slot_stride(const lbm_params* p);
+size_t state_bytes(const lbm_params* p);
+Coll make_coll(const lbm_params* p);
+Grid make_grid(const lbm_params* p);
 
 struct StepLaunch {
   void* F;           // population buffer

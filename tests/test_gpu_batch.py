@@ -1,0 +1,145 @@
+"""GPU tests of the batched path (lbm_batch_*): uneven instances stepped by one
+persistent kernel over a tile work-list, time loops replayed from a captured graph.
+
+The bar is bitwise: an instance inside a batch must end exactly where the same
+instance run alone in a context (lbm_create/lbm_step) ends, whatever the other
+instances, its admission time, the graph length or the tuned launch shape; the
+single-context path is itself checked against the oracle in test_gpu_parity.py.
+A Becker mix is also checked directly against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_16361_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def alone(case, steps, storage=None):
+    with binding.Solver(case.params, storage=storage) as s:
+        s.init(case.Q0)
+        s.step(steps)
+        f, st = s.populations()
+    assert st == steps
+    return f
+
+
+def mix():
+    """Uneven instances: sizes, both boundary kinds, both collisions, FP32 and FP16."""
+    cases = [
+        (inputs.random_smooth(300, 3, 2, seed=1, amp=0.06, bc=(1, 0, 0)), None),
+        (inputs.random_smooth(17, 9, 5, seed=2, amp=0.05), None),
+        (inputs.random_smooth(64, 4, 4, seed=3, amp=0.05, collision=inputs.BGK), None),
+        (inputs.becker(L=200, mach=2.5, ny=4, nz=4), None),
+        (inputs.random_smooth(33, 7, 3, seed=4, amp=0.05, bc=(1, 1, 0)), binding.LBM_STORE_F16),
+        (inputs.sod(n=128, ny=2, nz=3), None),
+    ]
+    return cases
+
+
+@pytest.mark.parametrize("graph_steps", [1, 16])
+def test_batch_equals_single_contexts_bitwise(graph_steps):
+    cases = mix()
+    steps = [37, 20, 41, 25, 30, 18]
+    admit = [0, 0, 5, 9, 9, 23]          # clock at which each instance joins
+    with binding.Batch(1 << 26, graph_steps=graph_steps) as b:
+        ids = {}
+        clock = 0
+        for t_admit in sorted(set(admit)):
+            if t_admit > clock:
+                say(f"batch run {t_admit - clock} steps (graph {graph_steps})")
+                b.run(t_admit - clock)
+                clock = t_admit
+            for k, (c, stg) in enumerate(cases):
+                if admit[k] == t_admit:
+                    ids[k] = b.add(c.params, c.Q0, steps[k], storage=stg)
+        say("batch run to the end")
+        b.run(max(a + s for a, s in zip(admit, steps)) - clock + 3)
+        for k, (c, stg) in enumerate(cases):
+            done, fin = b.query(ids[k])
+            assert fin and done == steps[k]
+            fb, st = b.populations(ids[k])
+            assert st == steps[k]
+            say(f"compare instance {k}")
+            fa = alone(c, steps[k], storage=stg)
+            assert np.array_equal(fa, fb), k
+            Qb = b.moments(ids[k])
+            with binding.Solver(c.params, storage=stg) as s:
+                s.init(c.Q0)
+                s.step(steps[k])
+                assert np.array_equal(s.moments(), Qb)
+
+
+def test_batch_autotune_keeps_state():
+    cases = mix()[:4]
+    with binding.Batch(1 << 26, graph_steps=8) as b:
+        ids = [b.add(c.params, c.Q0, 40) for c, _ in cases]
+        b.run(6)
+        say("autotune")
+        best, us, tried = b.autotune(trial_steps=8)
+        assert len(tried) >= 8 and us > 0
+        assert b.info()["tuning"] == best
+        assert b.info()["clock"] == 6
+        b.run(40)
+        for i, (c, _) in zip(ids, cases):
+            fb, st = b.populations(i)
+            assert st == 40
+            assert np.array_equal(fb, alone(c, 40)), i
+
+
+def test_batch_remove_and_reuse():
+    c1 = inputs.random_smooth(40, 5, 4, seed=8, amp=0.05)
+    c2 = inputs.random_smooth(30, 6, 4, seed=9, amp=0.05, bc=(0, 1, 0))
+    c3 = inputs.random_smooth(20, 5, 4, seed=10, amp=0.05)
+    p1 = binding.make_params(c1.params)
+    arena = binding.lbm_state_bytes(p1) * 2 + (1 << 20)
+    with binding.Batch(arena, max_instances=2) as b:
+        i1 = b.add(c1.params, c1.Q0, 10)
+        i2 = b.add(c2.params, c2.Q0, 25)
+        with pytest.raises(binding.LbmError) as e:
+            b.add(c3.params, c3.Q0, 5)          # descriptor table full
+        assert e.value.status == binding.LBM_ENOMEM
+        b.run(12)
+        assert b.query(i1) == (10, True) and b.query(i2) == (12, False)
+        b.remove(i1)
+        i3 = b.add(c3.params, c3.Q0, 9)          # reuses the freed slot and arena run
+        b.run(13)
+        assert b.query(i2) == (25, True) and b.query(i3) == (9, True)
+        assert np.array_equal(b.populations(i2)[0], alone(c2, 25))
+        assert np.array_equal(b.populations(i3)[0], alone(c3, 9))
+        with pytest.raises(binding.LbmError):
+            b.query(i1 + 7)
+        info = b.info()
+        assert info["live_instances"] == 2 and info["active_instances"] == 0
+
+
+def test_batch_arena_full():
+    c = inputs.random_smooth(64, 8, 8, seed=1)
+    need = binding.lbm_state_bytes(binding.make_params(c.params))
+    with binding.Batch(need + need // 2) as b:
+        b.add(c.params, c.Q0, 3)
+        with pytest.raises(binding.LbmError) as e:
+            b.add(c.params, c.Q0, 3)
+        assert e.value.status == binding.LBM_ENOMEM
+
+
+def test_becker_mix_against_oracle():
+    """Small Becker tubes of the batched workload's kind (zero-gradient ends,
+    regularized collision with sensor, Pr = 3/4) against the FP64 oracle."""
+    cases = [inputs.becker(L=L, mach=m, ny=4, nz=4) for L, m in ((96, 1.5), (160, 3.0), (128, 5.0))]
+    with binding.Batch(1 << 26, graph_steps=16) as b:
+        ids = [b.add(c.params, c.Q0, 300) for c in cases]
+        b.run(300)
+        for i, c in zip(ids, cases):
+            say(f"becker L={c.params['nx']} vs oracle")
+            Q = b.moments(i)
+            f, _ = oracle.run(c.params, oracle.init(c.params, c.Q0), 300)
+            Qo = oracle.moments(c.params, f)
+            for k in (0, 1, 4):
+                e = np.linalg.norm(Q[k] - Qo[k]) / np.linalg.norm(Qo[k])
+                assert e <= 2e-5, (c.params["nx"], k, e)
