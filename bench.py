@@ -122,6 +122,55 @@ def bench_batch(count=64, steps=5000, seed=0, stream=None):
     return out
 
 
+def bench_precision(stream, n=128, steps=4000, diag_every=50, oracle_steps=200):
+    """FP16 shifted storage against FP32 storage (both FP32 arithmetic) on the
+    compressible Taylor-Green vortex at n^3, and both against the FP64 oracle over
+    its first oracle_steps steps: relative L2 over the diagnostic time series of
+    E_k, eps_s and eps_d, and of the conserved fields at the end of the oracle run."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2609_16361_amd import binding, inputs
+    case = inputs.tgv(n=n, steps=steps, diag_every=diag_every)
+    series, fields, rates = {}, {}, {}
+    for name, stg in (("f32", binding.LBM_STORE_F32), ("f16", binding.LBM_STORE_F16)):
+        with binding.Solver(case.params, storage=stg, stream=stream.cuda_stream) as s:
+            s.init(case.Q0)
+            s.step(oracle_steps, diag_every)
+            fields[name] = s.moments()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(steps - oracle_steps, diag_every)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rates[name] = case.cells * (steps - oracle_steps) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+            recs, st = s.diagnostics()
+            assert st == binding.LBM_OK
+            series[name] = np.array([[r["Ek"], r["eps_s"], r["eps_d"]] for r in recs]) / case.cells
+    f, dor = oracle.run(case.params, oracle.init(case.params, case.Q0), oracle_steps, diag_every)
+    Qo = oracle.moments(case.params, f)
+    so = dor[:, :3] / case.cells
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    k0 = 1  # the first record is the equilibrium start, where the gradients are zero
+    out = {"workload": f"compressible Taylor-Green {n}^3, {steps} steps, diagnostics every {diag_every}",
+           "glups": rates,
+           "f16_vs_f32_series": {q: rel(series["f16"][k0:, i], series["f32"][k0:, i])
+                                 for i, q in enumerate(("Ek", "eps_s", "eps_d"))},
+           "vs_oracle_series": {name: {q: rel(series[name][k0:len(so), i], so[k0:, i])
+                                       for i, q in enumerate(("Ek", "eps_s", "eps_d"))}
+                                for name in ("f32", "f16")},
+           "vs_oracle_fields": {name: [rel(fields[name][k], Qo[k]) for k in range(5)]
+                                for name in ("f32", "f16")},
+           "oracle_steps": oracle_steps,
+           "Ek_final": {name: float(series[name][-1, 0] * case.meta["ek_scale"]) for name in series},
+           "tc_final": steps * case.meta["tc_per_step"]}
+    return out
+
+
 def measured_traffic():
     """HBM bytes per launch of the collide-and-stream kernel from the committed
     FETCH_SIZE/WRITE_SIZE counter runs, or None if the kernel sources changed since."""
@@ -150,6 +199,9 @@ def main():
     ap.add_argument("--no-bw-probe", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Becker workload")
     ap.add_argument("--batch-only", action="store_true", help="only the batched Becker workload")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only the FP16-storage precision study (128^3 vortex)")
+    ap.add_argument("--fp16", action="store_true", help="FP16 population storage for the main workload")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run the streaming-copy probe on BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -174,12 +226,17 @@ def main():
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(stream=stream)}), flush=True)
         return
+    if args.precision_only:
+        print(json.dumps({"precision": bench_precision(stream)}), flush=True)
+        return
 
     case = inputs.tgv(n=args.n, diag_every=args.diag_every)
     cells = case.cells
+    storage = binding.LBM_STORE_F16 if args.fp16 else binding.LBM_STORE_F32
+    bytes_per_lup = BYTES_PER_LUP_F32 / 2 if args.fp16 else BYTES_PER_LUP_F32
     solver = binding.Solver(case.params, stream=stream.cuda_stream, block=args.block,
                             nontemporal=None if args.nontemporal is None else bool(args.nontemporal),
-                            layout_pad=args.layout_pad)
+                            layout_pad=args.layout_pad, storage=storage)
     solver.init(case.Q0)
     del case.Q0
 
@@ -204,7 +261,7 @@ def main():
 
     glups = cells * args.steps / (ms * 1e-3) / 1e9
     avg_launch_ms = ms / args.steps
-    achieved_gbs = BYTES_PER_LUP_F32 * cells / (avg_launch_ms * 1e-3) / 1e9
+    achieved_gbs = bytes_per_lup * cells / (avg_launch_ms * 1e-3) / 1e9
 
     bw = None
     if not args.no_bw_probe:
@@ -221,9 +278,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if not args.fp16 else "f32 arithmetic, f16 storage",
         "data": "synthetic (analytic compressible Taylor-Green initial field)",
-        "config": {"workload": f"compressible Taylor-Green vortex {args.n}^3 periodic FP32, Mach 1.25, "
+        "config": {"workload": f"compressible Taylor-Green vortex {args.n}^3 periodic "
+                               f"{'FP16-storage' if args.fp16 else 'FP32'}, Mach 1.25, "
                                f"Re 1600, regularized collision + sensor, diagnostics every "
                                f"{args.diag_every} steps",
                    "cells": cells, "steps": args.steps, "diag_every": args.diag_every,
@@ -232,8 +290,9 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch",
-                     "bytes_per_lup": BYTES_PER_LUP_F32, "avg_launch_ms": round(avg_launch_ms, 5)},
+                     "traffic": None if args.fp16 else measured_traffic(),
+                     "traffic_unit": "bytes per launch",
+                     "bytes_per_lup": bytes_per_lup, "avg_launch_ms": round(avg_launch_ms, 5)},
         "host_wall_s": round(t_host, 3),
         "copy_bw_gbs": None if bw is None else round(bw, 1),
         "diag_records": len(recs),

@@ -2,6 +2,7 @@
 // stream binding, step scheduling and the diagnostic record queue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -113,7 +114,60 @@ Coll make_coll(const lbm_params* p) {
   c.rho_ref = (float)p->rho_ref;
   c.E_ref = (float)p->E_ref;
   c.sutherland = p->mu_law == LBM_MU_SUTHERLAND ? 1 : 0;
+  for (int k = 0; k < 5; ++k) c.sc[k] = c.isc[k] = 1.0f;
   return c;
+}
+
+void set_storage_scales(Coll& c, const unsigned maxabs_bits[5]) {
+  float mx[5], top = 0.0f;
+  for (int k = 0; k < 5; ++k) {
+    std::memcpy(&mx[k], &maxabs_bits[k], sizeof(float));
+    if (!(mx[k] < 3.0e38f)) mx[k] = 0.0f;  // non-finite input: leave it unscaled
+    top = std::max(top, mx[k]);
+  }
+  for (int k = 0; k < 5; ++k) {
+    // a field that is identically zero takes its scale from the largest field
+    const float m = std::max(mx[k], 1e-3f * top);
+    int e = 0;
+    if (m > 0.0f) {
+      std::frexp(m, &e);  // m = f * 2^e, f in [0.5, 1)
+      e = 10 - e;         // m * 2^e in [512, 1024)
+      e = std::min(std::max(e, -100), 100);
+    }
+    c.sc[k] = std::ldexp(1.0f, e);
+    c.isc[k] = std::ldexp(1.0f, -e);
+  }
+}
+
+static lbm_status read_maxabs(Coll& c, unsigned* d, hipStream_t s) {
+  unsigned h[5];
+  HIP_TRY(hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  set_storage_scales(c, h);
+  return LBM_OK;
+}
+
+lbm_status scales_from_fields(Coll& c, const Grid& g, const double* Q_dev, int64_t N, hipStream_t s) {
+  unsigned* d = nullptr;
+  if (hipMalloc((void**)&d, 5 * sizeof(unsigned)) != hipSuccess) return fail(LBM_ENOMEM, "hipMalloc failed");
+  lbm_status st = LBM_OK;
+  if (hipMemsetAsync(d, 0, 5 * sizeof(unsigned), s) != hipSuccess ||
+      launch_init_maxabs(g, c, Q_dev, N, d, s) != hipSuccess)
+    st = fail(LBM_EDEVICE, "storage-scale reduction failed");
+  if (st == LBM_OK) st = read_maxabs(c, d, s);
+  (void)hipFree(d);
+  return st;
+}
+
+lbm_status scales_from_pops(Coll& c, const float* f_dev, int64_t N, hipStream_t s) {
+  unsigned* d = nullptr;
+  if (hipMalloc((void**)&d, 5 * sizeof(unsigned)) != hipSuccess) return fail(LBM_ENOMEM, "hipMalloc failed");
+  lbm_status st = LBM_OK;
+  if (hipMemsetAsync(d, 0, 5 * sizeof(unsigned), s) != hipSuccess || launch_maxabs_pops(f_dev, N, d, s) != hipSuccess)
+    st = fail(LBM_EDEVICE, "storage-scale reduction failed");
+  if (st == LBM_OK) st = read_maxabs(c, d, s);
+  (void)hipFree(d);
+  return st;
 }
 
 Grid make_grid(const lbm_params* p) {
@@ -289,6 +343,10 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t nontemporal, int32_
 
 lbm_status lbm_init_fields_device(lbm_ctx* c, const double* Q_dev) {
   if (!c || !Q_dev) return fail(LBM_EINVAL, "ctx or Q is NULL");
+  if (c->p.storage == LBM_STORE_F16) {
+    lbm_status st = grlbm::scales_from_fields(c->c, c->g, Q_dev, c->N, c->stream);
+    if (st != LBM_OK) return st;
+  }
   HIP_TRY(grlbm::launch_init(c->F, c->p.storage == LBM_STORE_F16, c->g, c->c, Q_dev, c->N, c->stream));
   c->step = 0;
   c->ready = true;
@@ -421,8 +479,16 @@ lbm_status lbm_set_populations(lbm_ctx* c, const float* f, int64_t step) {
   lbm_status st = dev_alloc(&d, (size_t)35 * c->N, "populations");
   if (st != LBM_OK) return st;
   hipError_t e = hipMemcpyAsync(d, f, (size_t)35 * c->N * sizeof(float), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && c->p.storage == LBM_STORE_F16) {
+    st = grlbm::scales_from_pops(c->c, d, c->N, c->stream);
+    if (st != LBM_OK) {
+      (void)hipFree(d);
+      return st;
+    }
+  }
   if (e == hipSuccess)
-    e = grlbm::launch_scatter(c->F, c->p.storage == LBM_STORE_F16, c->g, c->N, (step & 1) != 0, d, c->stream);
+    e = grlbm::launch_scatter(c->F, c->p.storage == LBM_STORE_F16, c->g, c->c, c->N, (step & 1) != 0, d,
+                              c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(d);
   if (e != hipSuccess) return fail(LBM_EDEVICE, "population restore failed: %s", hipGetErrorString(e));

@@ -425,6 +425,14 @@ lbm_status lbm_batch_add(lbm_batch* b, const lbm_params* p, const double* Q, int
     return fail(LBM_ENOMEM, "staging allocation for the initial fields failed");
   }
   hipError_t e = hipMemcpyAsync(dq, Q, sizeof(double) * 5 * (size_t)N, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && p->storage == LBM_STORE_F16) {
+    st = grlbm::scales_from_fields(h.d.c, h.d.g, dq, N, b->stream);
+    if (st != LBM_OK) {
+      (void)hipFree(dq);
+      arena_free(b, off, bytes);
+      return st;
+    }
+  }
   if (e == hipSuccess)
     e = grlbm::launch_init(b->arena + off, p->storage == LBM_STORE_F16, h.d.g, h.d.c, dq, N, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);

@@ -45,6 +45,7 @@ struct Coll {
   float rho_min, p_min;
   float rho_ref, E_ref;
   int32_t sutherland;
+  float sc[5], isc[5];  // FP16 storage: stored value = g * sc[field] (powers of two)
 };
 
 struct Grid {
@@ -138,7 +139,10 @@ struct CellDiag {
 //              (eq. 6); grad u = X / rho, grad(rho u) = X + u (x) grad rho
 //   energy:    the scalar inversion of eq. 7 with the energy-row blocks of eq. 5
 // followed by the chain rule to grad T.
-template <int COLL, bool DIAG>
+// SCALED (FP16 storage): g holds the stored values g * sc[field]; the moments are
+// brought back with isc and the post-collision values leave multiplied by sc, so
+// the arithmetic in between is the same FP32 arithmetic as without scaling.
+template <int COLL, bool DIAG, bool SCALED = false>
 __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* d) {
   // line 1: moments (the shift cancels in the first moments)
   float dq[5], J[5][3];
@@ -149,6 +153,12 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
     J[k][0] = f[1] - f[2];
     J[k][1] = f[3] - f[4];
     J[k][2] = f[5] - f[6];
+    if constexpr (SCALED) {
+      dq[k] *= c.isc[k];
+      J[k][0] *= c.isc[k];
+      J[k][1] *= c.isc[k];
+      J[k][2] *= c.isc[k];
+    }
   }
   const float rho = c.rho_ref + dq[0];
   const float m0 = dq[1], m1 = dq[2], m2 = dq[3];
@@ -280,30 +290,33 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
   for (int k = 0; k < 5; ++k) {
     const float om = c.om[k == 0 ? 0 : (k == 4 ? 2 : 1)];
     float* f = g + 7 * k;
-    const float q8 = 0.125f * dq[k];
+    // output scale (exactly 1 without SCALED)
+    const float s = SCALED ? c.sc[k] : 1.0f;
+    const float q8 = (SCALED ? 0.125f * s : 0.125f) * dq[k];
+    const float h2 = SCALED ? 0.5f * s : 0.5f;
     if (COLL == 0) {
       // regularized: J* = omega_h Phi + (1 - omega_h) J
       const float oh = om - chi * (om - c.om_min);
       const float jx = J[k][0] + oh * (Phi[k][0] - J[k][0]);
       const float jy = J[k][1] + oh * (Phi[k][1] - J[k][1]);
       const float jz = J[k][2] + oh * (Phi[k][2] - J[k][2]);
-      f[0] = 0.25f * dq[k];
-      f[1] = q8 + 0.5f * jx;
-      f[2] = q8 - 0.5f * jx;
-      f[3] = q8 + 0.5f * jy;
-      f[4] = q8 - 0.5f * jy;
-      f[5] = q8 + 0.5f * jz;
-      f[6] = q8 - 0.5f * jz;
+      f[0] = (SCALED ? 0.25f * s : 0.25f) * dq[k];
+      f[1] = q8 + h2 * jx;
+      f[2] = q8 - h2 * jx;
+      f[3] = q8 + h2 * jy;
+      f[4] = q8 - h2 * jy;
+      f[5] = q8 + h2 * jz;
+      f[6] = q8 - h2 * jz;
     } else {
       // BGK: f <- f + omega (f_eq - f)
-      const float e0 = 0.25f * dq[k];
+      const float e0 = (SCALED ? 0.25f * s : 0.25f) * dq[k];
       f[0] += om * (e0 - f[0]);
-      f[1] += om * ((q8 + 0.5f * Phi[k][0]) - f[1]);
-      f[2] += om * ((q8 - 0.5f * Phi[k][0]) - f[2]);
-      f[3] += om * ((q8 + 0.5f * Phi[k][1]) - f[3]);
-      f[4] += om * ((q8 - 0.5f * Phi[k][1]) - f[4]);
-      f[5] += om * ((q8 + 0.5f * Phi[k][2]) - f[5]);
-      f[6] += om * ((q8 - 0.5f * Phi[k][2]) - f[6]);
+      f[1] += om * ((q8 + h2 * Phi[k][0]) - f[1]);
+      f[2] += om * ((q8 - h2 * Phi[k][0]) - f[2]);
+      f[3] += om * ((q8 + h2 * Phi[k][1]) - f[3]);
+      f[4] += om * ((q8 - h2 * Phi[k][1]) - f[4]);
+      f[5] += om * ((q8 + h2 * Phi[k][2]) - f[5]);
+      f[6] += om * ((q8 - h2 * Phi[k][2]) - f[6]);
     }
   }
   if constexpr (DIAG) {
@@ -338,7 +351,7 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
     }
   }
   CellDiag d;
-  collide<COLL, DIAG>(f, c, &d);
+  collide<COLL, DIAG, sizeof(T) == 2>(f, c, &d);
   if constexpr (DIAG) {
     vals[0] = d.ek;
     vals[1] = d.eps_s;

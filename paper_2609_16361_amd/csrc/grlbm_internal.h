@@ -44,8 +44,18 @@ hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const do
                        hipStream_t s);
 hipError_t launch_gather(const void* F, bool f16, const Grid& g, const Coll& c, int64_t N, bool odd,
                          int mode, float* out_f, double* out_q, hipStream_t s);
-hipError_t launch_scatter(void* F, bool f16, const Grid& g, int64_t N, bool odd, const float* in_f,
-                          hipStream_t s);
+hipError_t launch_scatter(void* F, bool f16, const Grid& g, const Coll& c, int64_t N, bool odd,
+                          const float* in_f, hipStream_t s);
+hipError_t launch_init_maxabs(const Grid& g, const Coll& c, const double* Q, int64_t N, unsigned* maxabs,
+                              hipStream_t s);
+hipError_t launch_maxabs_pops(const float* f, int64_t N, unsigned* maxabs, hipStream_t s);
+// FP16 storage: pick power-of-two scales so that each field's largest |g| maps into
+// [512, 1024) (64x headroom below the FP16 maximum, 2^-24 of it before subnormals).
+void set_storage_scales(Coll& c, const unsigned maxabs_bits[5]);
+// Scales from the initial fields Q (device) or from canonical populations f
+// (device); synchronises the stream to read the maxima back.
+lbm_status scales_from_fields(Coll& c, const Grid& g, const double* Q_dev, int64_t N, hipStream_t s);
+lbm_status scales_from_pops(Coll& c, const float* f_dev, int64_t N, hipStream_t s);
 hipError_t launch_copy(const void* a, void* b, int64_t bytes, hipStream_t s);
 
 }  // namespace grlbm

@@ -104,10 +104,19 @@ __global__ void __launch_bounds__(1024) k_finalize(const float* __restrict__ par
   if (threadIdx.x == 0) rec[j] = sm[0];
 }
 
-// Equilibrium of Q with the advective flux: g_i = w_i (Q - Q_ref + 4 c_i . Phi_adv).
+// Largest |v| per field, as the bit pattern of a non-negative float (which orders
+// like the value); the result does not depend on the order of the atomics.
+__device__ __forceinline__ void field_max(unsigned* maxabs, int k, float v) {
+  atomicMax(maxabs + k, __float_as_uint(fabsf(v)));
+}
+
+// Equilibrium of Q with the advective flux: g_i = w_i (Q - Q_ref + 4 c_i . Phi_adv),
+// stored times the field's storage scale.  With maxabs set, nothing is stored and
+// the largest |g| of each field is reduced instead (used to pick the FP16 scales).
 template <typename T>
 __global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
-                                               const double* __restrict__ Q, int64_t N) {
+                                               const double* __restrict__ Q, int64_t N,
+                                               unsigned* __restrict__ maxabs) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   const float rho = (float)Q[n];
@@ -127,15 +136,30 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
     Phi[4][cc] = (E + p) * u[cc];
   }
   for (int k = 0; k < 5; ++k) {
-    T* Fk = F + (int64_t)(7 * k) * g.S + n;
     const float q8 = 0.125f * dq[k];
-    Fk[0] = static_cast<T>(0.25f * dq[k]);
-    Fk[1 * g.S] = static_cast<T>(q8 + 0.5f * Phi[k][0]);
-    Fk[2 * g.S] = static_cast<T>(q8 - 0.5f * Phi[k][0]);
-    Fk[3 * g.S] = static_cast<T>(q8 + 0.5f * Phi[k][1]);
-    Fk[4 * g.S] = static_cast<T>(q8 - 0.5f * Phi[k][1]);
-    Fk[5 * g.S] = static_cast<T>(q8 + 0.5f * Phi[k][2]);
-    Fk[6 * g.S] = static_cast<T>(q8 - 0.5f * Phi[k][2]);
+    const float v[7] = {0.25f * dq[k],         q8 + 0.5f * Phi[k][0], q8 - 0.5f * Phi[k][0],
+                        q8 + 0.5f * Phi[k][1], q8 - 0.5f * Phi[k][1], q8 + 0.5f * Phi[k][2],
+                        q8 - 0.5f * Phi[k][2]};
+    if (maxabs) {
+      float m = 0.0f;
+      for (int i = 0; i < kQ; ++i) m = fmaxf(m, fabsf(v[i]));
+      field_max(maxabs, k, m);
+    } else {
+      T* Fk = F + (int64_t)(7 * k) * g.S + n;
+      for (int i = 0; i < kQ; ++i) Fk[(int64_t)i * g.S] = static_cast<T>(v[i] * c.sc[k]);
+    }
+  }
+}
+
+// Largest |f| per field of a canonical population array f[35][N].
+__global__ void __launch_bounds__(256) k_maxabs_pops(const float* __restrict__ f, int64_t N,
+                                                      unsigned* __restrict__ maxabs) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  for (int k = 0; k < 5; ++k) {
+    float m = 0.0f;
+    for (int i = 0; i < kQ; ++i) m = fmaxf(m, fabsf(f[(int64_t)(7 * k + i) * N + n]));
+    field_max(maxabs, k, m);
   }
 }
 
@@ -170,7 +194,7 @@ __global__ void __launch_bounds__(256) k_gather(const T* __restrict__ F, Grid g,
   for (int k = 0; k < 5; ++k) {
     float s = 0.0f;
     for (int i = 0; i < kQ; ++i) {
-      const float v = static_cast<float>(F[canon_off<T>(g, b, k, i, odd != 0)]);
+      const float v = static_cast<float>(F[canon_off<T>(g, b, k, i, odd != 0)]) * c.isc[k];
       if (mode == 0) out_f[(int64_t)(7 * k + i) * N + n] = v;
       s += v;
     }
@@ -182,7 +206,7 @@ __global__ void __launch_bounds__(256) k_gather(const T* __restrict__ F, Grid g,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_scatter(T* __restrict__ F, Grid g, int64_t N, int odd,
+__global__ void __launch_bounds__(256) k_scatter(T* __restrict__ F, Grid g, Coll c, int64_t N, int odd,
                                                   const float* __restrict__ in_f) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
@@ -191,7 +215,8 @@ __global__ void __launch_bounds__(256) k_scatter(T* __restrict__ F, Grid g, int6
   const Nbr b = make_nbr(g, x, y, z);
   for (int k = 0; k < 5; ++k)
     for (int i = 0; i < kQ; ++i)
-      F[canon_off<T>(g, b, k, i, odd != 0)] = static_cast<T>(in_f[(int64_t)(7 * k + i) * N + n]);
+      F[canon_off<T>(g, b, k, i, odd != 0)] =
+          static_cast<T>(in_f[(int64_t)(7 * k + i) * N + n] * c.sc[k]);
 }
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -257,9 +282,22 @@ hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const do
                        hipStream_t s) {
   const unsigned blocks = (unsigned)((N + 255) / 256);
   if (f16)
-    hipLaunchKernelGGL(k_init<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, c, Q, N);
+    hipLaunchKernelGGL(k_init<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, c, Q, N, nullptr);
   else
-    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, c, Q, N);
+    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, c, Q, N, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_maxabs(const Grid& g, const Coll& c, const double* Q, int64_t N, unsigned* maxabs,
+                              hipStream_t s) {
+  const unsigned blocks = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, nullptr, g, c, Q, N, maxabs);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxabs_pops(const float* f, int64_t N, unsigned* maxabs, hipStream_t s) {
+  const unsigned blocks = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL(k_maxabs_pops, dim3(blocks), dim3(256), 0, s, f, N, maxabs);
   return hipGetLastError();
 }
 
@@ -275,14 +313,14 @@ hipError_t launch_gather(const void* F, bool f16, const Grid& g, const Coll& c, 
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(void* F, bool f16, const Grid& g, int64_t N, bool odd, const float* in_f,
-                          hipStream_t s) {
+hipError_t launch_scatter(void* F, bool f16, const Grid& g, const Coll& c, int64_t N, bool odd,
+                          const float* in_f, hipStream_t s) {
   const unsigned blocks = (unsigned)((N + 255) / 256);
   if (f16)
-    hipLaunchKernelGGL(k_scatter<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, N, (int)odd,
+    hipLaunchKernelGGL(k_scatter<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, c, N, (int)odd,
                        in_f);
   else
-    hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, N, (int)odd, in_f);
+    hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, c, N, (int)odd, in_f);
   return hipGetLastError();
 }
 
