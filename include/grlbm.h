@@ -171,8 +171,8 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
 /* ------------------------------------------------------------------ batches
  * Many independent instances (different sizes, boundaries, parameters, storage
  * types and start times) advanced together: one persistent kernel per (collision,
- * storage) group walks a tile work-list (a tile is one block-width chunk of one
- * x-row of one instance), and time loops of `graph_steps` steps replay one captured
+ * storage) group walks a tile work-list (a tile is one block-width range of
+ * consecutive cells of one instance), and time loops of `graph_steps` steps replay one captured
  * HIP graph.  Every instance keeps its own step count: it is at its step 0 when
  * added, advances with each lbm_batch_run step until it has made the number of
  * steps it was added with, then stays frozen until removed.  Results are bitwise
@@ -181,7 +181,7 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
 typedef struct lbm_batch lbm_batch; /* opaque */
 
 typedef struct {
-  int32_t block;          /* threads per block = tile width in cells (64..1024)   */
+  int32_t block;          /* threads per block = cells per tile (64..1024)         */
   int32_t nontemporal;    /* nontemporal loads and stores                          */
   int32_t blocks_per_cu;  /* occupancy cap enforced by an LDS reservation (0 = off) */
   int32_t grid;           /* persistent grid size in blocks                        */

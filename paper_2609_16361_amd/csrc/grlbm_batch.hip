@@ -2,8 +2,8 @@
 //
 // One device arena holds the populations of every instance (the same SoA, AA
 // in-place layout as a single context).  A descriptor table and a tile work-list
-// live in device memory: a tile is one block-width chunk of one x-row of one
-// instance.  k_batch_step is a persistent kernel: a fixed grid loops over the tile
+// live in device memory: a tile is one block-width range of consecutive cells of
+// one instance.  k_batch_step is a persistent kernel: a fixed grid loops over the tile
 // list, and each block derives its instance's AA parity and whether it is active
 // from a device-resident clock, so one launch advances every active instance by one
 // step whatever its size, boundaries, parameters or age.  Consecutive launches on
@@ -32,14 +32,33 @@ struct BatchInst {
   int64_t off;      // element offset of the instance's slot 0 in the arena
   int64_t t_start;  // clock value at which the instance was at its step 0
   int64_t t_end;    // clock value at which it has completed all its steps
-  int32_t nxb;      // x-chunks per row
+  double inv_nx;    // 1/nx and 1/ny for the cell-index decomposition
+  double inv_ny;
+  int32_t cells;    // nx * ny * nz
   int32_t pad_;
 };
 
+// A tile is `blockDim.x` consecutive cell indices of one instance (it may span
+// several x-rows), so short rows leave no lane idle.
 struct BatchTile {
   int32_t inst;
-  int32_t chunk;  // chunk index within the instance: row * nxb + x-chunk
+  int32_t tile;  // tile index within the instance: cells [tile * blockDim.x, ...)
 };
+
+// q = n / d and r = n % d for 0 <= n < 2^31: the FP64 product is within one of the
+// quotient, one correction step makes it exact.
+__device__ __forceinline__ int div_exact(int n, int d, double inv_d, int& r) {
+  int q = (int)((double)n * inv_d);
+  r = n - q * d;
+  if (r < 0) {
+    --q;
+    r += d;
+  } else if (r >= d) {
+    ++q;
+    r -= d;
+  }
+  return q;
+}
 
 template <int COLL, typename T, bool NT>
 __global__ void __launch_bounds__(1024) k_batch_step(T* __restrict__ arena, const BatchInst* __restrict__ insts,
@@ -53,14 +72,13 @@ __global__ void __launch_bounds__(1024) k_batch_step(T* __restrict__ arena, cons
     const BatchInst* I = insts + bt.inst;
     const int64_t ts = I->t_start;
     if (t < ts || t >= I->t_end) continue;
+    const int n = bt.tile * (int)blockDim.x + (int)threadIdx.x;
+    if (n >= I->cells) continue;
     const Grid g = I->g;
-    const int nxb = I->nxb;
-    const int row = bt.chunk / nxb;
-    const int x = (bt.chunk - row * nxb) * (int)blockDim.x + (int)threadIdx.x;
-    if (x >= g.nx) continue;
+    int x, y;
+    const int row = div_exact(n, g.nx, I->inv_nx, x);
+    const int z = div_exact(row, g.ny, I->inv_ny, y);
     const Coll c = I->c;
-    const int y = row % g.ny;
-    const int z = row / g.ny;
     T* F = arena + I->off;
     // the same instantiation as a single context uses for this instance, so the
     // arithmetic (and its FMA contraction) is identical and so are the results
@@ -131,10 +149,9 @@ struct lbm_batch {
 
 namespace {
 
-int32_t chunks_per_row(const lbm_params* p, int block) { return (p->nx + block - 1) / block; }
-
 int64_t inst_tiles(const lbm_params* p, int block) {
-  return (int64_t)chunks_per_row(p, block) * p->ny * p->nz;
+  const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+  return (n + block - 1) / block;
 }
 
 lbm_status upload(lbm_batch* b) {
@@ -143,7 +160,6 @@ lbm_status upload(lbm_batch* b) {
   for (int32_t id = 0; id < (int32_t)b->insts.size(); ++id) {
     HostInst& h = b->insts[id];
     if (!h.live) continue;
-    h.d.nxb = chunks_per_row(&h.p, b->tune.block);
     // an instance that has completed its steps keeps its slot but no tiles
     if (h.d.t_end <= b->clock) continue;
     const int64_t n = inst_tiles(&h.p, b->tune.block);
@@ -417,8 +433,10 @@ lbm_status lbm_batch_add(lbm_batch* b, const lbm_params* p, const double* Q, int
   h.d.off = (int64_t)(off / el);
   h.d.t_start = b->clock;
   h.d.t_end = b->clock + steps;
-  h.d.nxb = chunks_per_row(p, b->tune.block);
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  h.d.cells = (int32_t)N;
+  h.d.inv_nx = 1.0 / p->nx;
+  h.d.inv_ny = 1.0 / p->ny;
   double* dq = nullptr;
   if (hipMalloc((void**)&dq, sizeof(double) * 5 * (size_t)N) != hipSuccess) {
     arena_free(b, off, bytes);

@@ -322,3 +322,95 @@ def random_smooth(nx, ny, nz, seed=0, amp=0.05, bc=(PERIODIC, PERIODIC, PERIODIC
                       omega_min=omega_min, p_min=1e-4 * p0, rho_ref=1.0,
                       E_ref=p0 / (gamma - 1.0))
     return Case("random", prm, Q, 0, 0, dict(seed=seed))
+
+
+# ------------------------------------------------------------------ served requests
+def riemann_max_speed(left, right, gamma=1.4):
+    """Fastest signal speed of a Riemann problem from left/right = (rho, u, p): star
+    pressure by Newton iteration on the wave-jump function (shock branch from
+    Rankine-Hugoniot, rarefaction branch isentropic), then the largest of the outer
+    wave speeds and |u*| + c* on either side.  Used only to choose the time step."""
+    def jump(p, rho, pk):
+        c = math.sqrt(gamma * pk / rho)
+        if p > pk:
+            A = 2.0 / ((gamma + 1.0) * rho)
+            B = (gamma - 1.0) / (gamma + 1.0) * pk
+            return (p - pk) * math.sqrt(A / (p + B)), math.sqrt(A / (B + p)) * (1 - (p - pk) / (2 * (B + p)))
+        e = (gamma - 1.0) / (2.0 * gamma)
+        return (2 * c / (gamma - 1.0) * ((p / pk) ** e - 1.0),
+                (p / pk) ** (-(gamma + 1.0) / (2 * gamma)) / (rho * c))
+    rl, ul, pl = left
+    rr, ur, pr = right
+    p = 0.5 * (pl + pr)
+    for _ in range(60):
+        fl, dl = jump(p, rl, pl)
+        fr, dr = jump(p, rr, pr)
+        p = max(p - (fl + fr + ur - ul) / (dl + dr), 1e-12 * (pl + pr))
+    fl, _ = jump(p, rl, pl)
+    fr, _ = jump(p, rr, pr)
+    us = 0.5 * (ul + ur) + 0.5 * (fr - fl)
+    speeds = []
+    for rho, u, pk, sgn in ((rl, ul, pl, -1.0), (rr, ur, pr, 1.0)):
+        c = math.sqrt(gamma * pk / rho)
+        if p > pk:
+            speeds.append(abs(u + sgn * c * math.sqrt((gamma + 1) / (2 * gamma) * p / pk + (gamma - 1) / (2 * gamma))))
+            rs = rho * ((p / pk + (gamma - 1) / (gamma + 1)) / ((gamma - 1) / (gamma + 1) * p / pk + 1))
+        else:
+            speeds.append(abs(u) + c)
+            rs = rho * (p / pk) ** (1.0 / gamma)
+        speeds.append(abs(us) + math.sqrt(gamma * p / rs))
+    return max(speeds)
+
+
+def sod_variant(n, rho_ratio, p_ratio, ny=4, nz=4, lattice_speed=0.28, **kw):
+    """Sod-type tube with left/right density and pressure ratios (right state 0.125,
+    0.1 scaled by the ratios); r = dt/dx keeps the fastest wave at lattice_speed."""
+    left = (0.125 * rho_ratio, 0.1 * p_ratio)
+    right = (0.125, 0.1)
+    smax = riemann_max_speed((left[0], 0.0, left[1]), (right[0], 0.0, right[1]))
+    r = lattice_speed / smax
+    return sod(n=n, ny=ny, nz=nz, r=r, left=left, right=right, **kw)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float     # seconds after the trace starts
+    kind: str
+    case: Case
+    steps: int
+    storage: int       # 0 FP32, 1 FP16
+
+
+def serving_trace(count=1000, rate=50.0, seed=1, steps_range=(1000, 20000), mix=(0.4, 0.4, 0.2),
+                  sod_n=(256, 4096), tgv_n=(32, 128), tgv_mach=(0.5, 1.5), becker_mach=(1.5, 5.0),
+                  becker_L=(512, 8192), fp16_share=0.5, tgv_tc_max=20.0):
+    """Seeded Poisson request stream: 40% Sod variants (n x 4 x 4, left/right density
+    and pressure ratios log-uniform on [1, 100]), 40% Taylor-Green vortices (n^3,
+    Mach uniform, time step such that the request ends by t_c = tgv_tc_max), 20%
+    Becker shocks (Mach uniform); steps uniform; FP32 or FP16 storage per request."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(count):
+        t += rng.exponential(1.0 / rate)
+        u = rng.uniform()
+        steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        storage = 1 if rng.uniform() < fp16_share else 0
+        if u < mix[0]:
+            n = int(rng.integers(sod_n[0], sod_n[1] + 1))
+            rr = float(np.exp(rng.uniform(0, math.log(100))))
+            pr = float(np.exp(rng.uniform(0, math.log(100))))
+            case, kind = sod_variant(n, rr, pr), "sod"
+        elif u < mix[0] + mix[1]:
+            n = int(rng.integers(tgv_n[0], tgv_n[1] + 1))
+            m = float(rng.uniform(*tgv_mach))
+            # the requested steps cover at most t_c = 20 (the horizon of Sec. 3.3)
+            r = min(TGV_LATTICE_SPEED / (1.0 + 1.0 / m), tgv_tc_max / (steps * 2.0 * math.pi / n))
+            case, kind = tgv(n=n, mach=m, steps=steps, diag_every=0, r=r), "tgv"
+        else:
+            L = int(rng.integers(becker_L[0], becker_L[1] + 1))
+            m = float(rng.uniform(*becker_mach))
+            case, kind = becker(L=L, mach=m), "becker"
+        out.append(Request(rid, t, kind, case, steps, storage))
+    return out

@@ -1,0 +1,191 @@
+"""Continuous-batching solve server over one lbm_batch.
+
+Requests (an initial state, a step count, a storage type) arrive over time.  The
+serving loop admits every request that has arrived, in arrival order, as long as
+its populations fit in the HBM budget (the batch arena) and the active-cell cap
+allows; it then advances the whole batch by one graph-captured chunk of steps
+(every admitted instance overlaps with the others on the device), retires the
+instances that have made their steps, reads their conserved fields back and frees
+their memory for the next arrivals.  A result is exactly what the same request
+gives alone: the batch updates each instance with the same arithmetic as a single
+context, and an instance freezes when it reaches its own step count.
+
+The loop runs on the wall clock (arrival times are seconds after start); latency
+is completion minus arrival.  A stand-in backend with the same methods as
+binding.Batch can replace the GPU (the CPU tests use one).
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ENOMEM = -2  # lbm_status LBM_ENOMEM
+
+
+@dataclass
+class Outcome:
+    rid: int
+    kind: str
+    storage: int
+    cells: int
+    steps: int
+    arrival: float
+    admitted: float = math.nan
+    completed: float = math.nan
+    ok: bool = False
+    result: object = None       # whatever the result handler returned
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.arrival
+
+
+@dataclass
+class ServeStats:
+    outcomes: list = field(default_factory=list)
+    wall_s: float = 0.0
+    chunks: int = 0
+    max_active: int = 0
+    peak_bytes: int = 0
+
+    def summary(self) -> dict:
+        done = [o for o in self.outcomes if o.ok]
+        lat = np.array([o.latency for o in done]) if done else np.array([math.nan])
+        first = min(o.arrival for o in self.outcomes) if self.outcomes else 0.0
+        last = max((o.completed for o in done), default=first)
+        span = max(last - first, 1e-9)
+        lups = sum(o.cells * o.steps for o in done)
+        return {"requests": len(self.outcomes), "completed": len(done),
+                "failed": len(self.outcomes) - len(done),
+                "solves_per_s": len(done) / span, "span_s": span,
+                "glups": lups / span / 1e9,
+                "latency_p50_s": float(np.percentile(lat, 50)),
+                "latency_p99_s": float(np.percentile(lat, 99)),
+                "latency_mean_s": float(np.mean(lat)),
+                "chunks": self.chunks, "max_active": self.max_active,
+                "peak_arena_bytes": self.peak_bytes, "wall_s": self.wall_s}
+
+
+def state_bytes(params: dict, storage: int) -> int:
+    """Device bytes of one instance (35 arrays padded to 256 B) -- mirrors
+    lbm_state_bytes without a device call."""
+    n = int(params["nx"]) * int(params["ny"]) * int(params["nz"])
+    el = 2 if storage else 4
+    align = 256 // el
+    s = (n + int(params.get("layout_pad", 0)) + align - 1) // align * align
+    return 35 * el * s
+
+
+class Server:
+    """backend: object with add(params, Q, steps, storage) -> id, run(n), query(id)
+    -> (done, finished), moments(id) -> Q, remove(id), and `arena_bytes`."""
+
+    def __init__(self, backend, arena_bytes: int, max_active_cells: int | None = None,
+                 chunk_steps: int = 50, result_handler=None, clock=time.perf_counter,
+                 sync=None, max_instances: int = 4096):
+        self.b = backend
+        self.arena_bytes = int(arena_bytes)
+        self.max_cells = max_active_cells
+        self.chunk = int(chunk_steps)
+        self.handle = result_handler or (lambda req, Q: bool(np.isfinite(Q).all()))
+        self.clock = clock
+        self.sync = sync or (lambda: None)
+        self.max_instances = max_instances
+
+    def serve(self, requests) -> ServeStats:
+        reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        out = {r.rid: Outcome(r.rid, r.kind, r.storage, r.case.cells, r.steps, r.arrival) for r in reqs}
+        pending = list(reqs)
+        active = {}                 # instance id -> (request, bytes)
+        used_bytes = 0
+        used_cells = 0
+        st = ServeStats()
+        t0 = self.clock()
+        while pending or active:
+            now = self.clock() - t0
+            # admission: arrived requests in order while memory and the cell cap allow
+            while pending and pending[0].arrival <= now:
+                r = pending[0]
+                nb = state_bytes(r.case.params, r.storage)
+                if nb > self.arena_bytes:
+                    out[r.rid].ok = False        # can never fit: rejected
+                    out[r.rid].completed = now
+                    pending.pop(0)
+                    continue
+                if used_bytes + nb > self.arena_bytes or len(active) >= self.max_instances:
+                    break
+                if self.max_cells is not None and active and used_cells + r.case.cells > self.max_cells:
+                    break
+                try:
+                    iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=r.storage)
+                except RuntimeError as e:
+                    # no free run of that size yet (fragmentation): wait for retirements
+                    if getattr(e, "status", None) == ENOMEM and active:
+                        break
+                    raise
+                pending.pop(0)
+                active[iid] = (r, nb)
+                used_bytes += nb
+                used_cells += r.case.cells
+                out[r.rid].admitted = self.clock() - t0
+            st.max_active = max(st.max_active, len(active))
+            st.peak_bytes = max(st.peak_bytes, used_bytes)
+            if not active:
+                # idle until the next arrival
+                wait = pending[0].arrival - (self.clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.05))
+                continue
+            # one chunk (a graph replay) for everything on the device; an instance that
+            # reaches its step count inside the chunk stays frozen there
+            self.b.run(self.chunk)
+            st.chunks += 1
+            self.sync()
+            tnow = self.clock() - t0
+            for iid in [i for i in active if self.b.query(i)[1]]:
+                r, nb = active.pop(iid)
+                Q = self.b.moments(iid)
+                o = out[r.rid]
+                o.completed = tnow
+                res = self.handle(r, Q)
+                o.ok = bool(res) if isinstance(res, (bool, np.bool_)) else True
+                o.result = res
+                self.b.remove(iid)
+                used_bytes -= nb
+                used_cells -= r.case.cells
+        st.wall_s = self.clock() - t0
+        st.outcomes = [out[r.rid] for r in reqs]
+        return st
+
+
+def serve_sequential(requests, solver_factory, result_handler=None, clock=time.perf_counter,
+                     sync=None) -> ServeStats:
+    """Baseline: the same requests one at a time in arrival order, each in its own
+    single context made by solver_factory(params) (plain FP32)."""
+    handle = result_handler or (lambda req, Q: bool(np.isfinite(Q).all()))
+    sync = sync or (lambda: None)
+    reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    st = ServeStats()
+    t0 = clock()
+    for r in reqs:
+        now = clock() - t0
+        if r.arrival > now:
+            time.sleep(r.arrival - now)
+        o = Outcome(r.rid, r.kind, 0, r.case.cells, r.steps, r.arrival)
+        o.admitted = clock() - t0
+        with solver_factory(r.case.params) as s:
+            s.init(r.case.Q0)
+            s.step(r.steps)
+            sync()
+            Q = s.moments()
+        o.completed = clock() - t0
+        res = handle(r, Q)
+        o.ok = bool(res) if isinstance(res, (bool, np.bool_)) else True
+        o.result = res
+        st.outcomes.append(o)
+        st.max_active = 1
+    st.wall_s = clock() - t0
+    return st

@@ -1,0 +1,150 @@
+"""Serving loop logic on the CPU with a stand-in backend (no GPU): admission in
+arrival order under the HBM budget and the active-cell cap, overlap of requests,
+retirement at each request's own step count, latency bookkeeping, rejection of a
+request that can never fit, and the served trace generator."""
+import numpy as np
+import pytest
+
+from paper_2609_16361_amd import inputs, serve
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeBatch:
+    """Instances advance one step per run step; a step costs `dt` fake seconds."""
+
+    def __init__(self, clock, dt=1e-3):
+        self.clock, self.dt = clock, dt
+        self.inst, self.next_id, self.log = {}, 0, []
+
+    def add(self, params, Q, steps, storage=0):
+        i = self.next_id
+        self.next_id += 1
+        self.inst[i] = [0, steps, Q]
+        self.log.append(("add", i, self.clock.t))
+        return i
+
+    def run(self, n):
+        for v in self.inst.values():
+            v[0] = min(v[1], v[0] + n)
+        self.clock.t += n * self.dt
+
+    def query(self, i):
+        done, steps, _ = self.inst[i]
+        return done, done >= steps
+
+    def moments(self, i):
+        return self.inst[i][2] + self.inst[i][0]
+
+    def remove(self, i):
+        self.log.append(("remove", i, self.clock.t))
+        del self.inst[i]
+
+
+def make_req(rid, arrival, cells, steps, storage=0):
+    nx = cells // 16
+    case = inputs.Case("x", dict(nx=nx, ny=4, nz=4, layout_pad=0), np.zeros((5, 4, 4, nx)), steps)
+    return inputs.Request(rid, arrival, "x", case, steps, storage)
+
+
+def test_fifo_budget_and_overlap():
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    reqs = [make_req(i, 0.01 * i, 1600, 100 + 50 * i) for i in range(6)]
+    one = serve.state_bytes(reqs[0].case.params, 0)
+    srv = serve.Server(fb, arena_bytes=3 * one, chunk_steps=10, clock=clk)
+    st = srv.serve(reqs)
+    s = st.summary()
+    assert s["completed"] == 6 and s["failed"] == 0
+    assert st.max_active == 3                       # budget caps concurrency at 3
+    adds = [i for (what, i, t) in fb.log if what == "add"]
+    assert adds == sorted(adds)                     # admitted in arrival order
+    for o in st.outcomes:
+        assert o.admitted >= o.arrival - 1e-12
+        assert o.completed >= o.admitted
+        # results are taken at the request's own step count, not the chunk end
+        assert np.all(o.result)
+    # each request needed at least its own steps of device time
+    for r, o in zip(reqs, st.outcomes):
+        assert o.completed - o.admitted >= r.steps * fb.dt - 1e-9
+
+
+def test_results_are_exact_step_counts():
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    reqs = [make_req(i, 0.0, 320, s) for i, s in enumerate((7, 33, 50, 51))]
+    got = {}
+
+    def handler(req, Q):
+        got[req.rid] = Q.flat[0]
+        return True
+
+    serve.Server(fb, arena_bytes=1 << 30, chunk_steps=16, clock=clk, result_handler=handler).serve(reqs)
+    assert got == {0: 7, 1: 33, 2: 50, 3: 51}
+
+
+def test_cell_cap_and_rejection():
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    reqs = [make_req(0, 0.0, 1600, 40), make_req(1, 0.0, 1600, 40), make_req(2, 0.0, 16000, 10)]
+    one = serve.state_bytes(reqs[0].case.params, 0)
+    srv = serve.Server(fb, arena_bytes=4 * one, max_active_cells=2000, chunk_steps=8, clock=clk)
+    st = srv.serve(reqs)
+    assert st.max_active == 1                     # the cell cap admits one at a time
+    assert [o.ok for o in st.outcomes] == [True, True, False]   # the big one never fits
+
+
+def test_sequential_baseline_fifo():
+    clk = FakeClock()
+
+    class Solver:
+        def __init__(self, params):
+            self.n = 0
+
+        def __enter__(self):
+            return self
+
+        def __exit__(self, *a):
+            pass
+
+        def init(self, Q):
+            self.Q = Q
+
+        def step(self, n):
+            self.n += n
+            clk.t += n * 1e-3
+
+        def moments(self):
+            return self.Q + self.n
+
+    reqs = [make_req(i, 0.0, 320, 10 * (i + 1)) for i in range(4)]
+    st = serve.serve_sequential(reqs, Solver, clock=clk)
+    lat = [o.latency for o in st.outcomes]
+    assert lat == sorted(lat)                      # FIFO: later requests wait longer
+    assert st.summary()["completed"] == 4
+
+
+def test_serving_trace_mix():
+    tr = inputs.serving_trace(count=40, seed=3, tgv_n=(16, 24), sod_n=(64, 96), becker_L=(64, 96))
+    kinds = {k: sum(1 for r in tr if r.kind == k) for k in ("sod", "tgv", "becker")}
+    assert sum(kinds.values()) == 40 and all(v > 0 for v in kinds.values())
+    arr = np.array([r.arrival for r in tr])
+    assert np.all(np.diff(arr) > 0)
+    assert 0.3 < arr[-1] < 2.0                     # mean rate 50/s
+    assert all(1000 <= r.steps <= 20000 for r in tr)
+    assert {r.storage for r in tr} == {0, 1}
+    for r in tr:
+        assert r.case.Q0.shape == (5,) + r.case.shape and np.isfinite(r.case.Q0).all()
+
+
+def test_riemann_max_speed_sod():
+    # Sod: fastest signal is u* + c* behind the shock, about 2.19 (exact star state
+    # p* = 0.30313, u* = 0.92745)
+    s = inputs.riemann_max_speed((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    assert s == pytest.approx(2.19, abs=0.02)
