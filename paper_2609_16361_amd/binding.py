@@ -89,7 +89,7 @@ SIGNATURES = {
     "lbm_diagnostics": (ctypes.c_int, [_vp, _P(lbm_diag), ctypes.c_int32, _P(ctypes.c_int32)]),
     "lbm_get_populations": (ctypes.c_int, [_vp, _P(ctypes.c_float), _P(ctypes.c_int64)]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _P(ctypes.c_float), ctypes.c_int64]),
-    "lbm_set_launch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_set_launch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "lbm_get_step": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "lbm_destroy": (ctypes.c_int, [_vp]),
     "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_double)]),
@@ -240,8 +240,10 @@ def lbm_set_populations(ctx: int, f: np.ndarray, step: int) -> None:
            "lbm_set_populations")
 
 
-def lbm_set_launch(ctx: int, block: int, nontemporal: bool, blocks_per_cu: int = 0) -> None:
-    _check(load().lbm_set_launch(ctx, int(block), int(bool(nontemporal)), int(blocks_per_cu)),
+def lbm_set_launch(ctx: int, block: int, nontemporal: bool, blocks_per_cu: int = 0,
+                   odd_rows: bool = True) -> None:
+    _check(load().lbm_set_launch(ctx, int(block), int(bool(nontemporal)), int(blocks_per_cu),
+                                 int(bool(odd_rows))),
            "lbm_set_launch")
 
 
@@ -272,14 +274,14 @@ class Solver:
 
     def __init__(self, params: dict, stream: int | None = None, storage: int | None = None,
                  block: int | None = None, nontemporal: bool | None = None, layout_pad: int = 0,
-                 blocks_per_cu: int = 0):
+                 blocks_per_cu: int = 0, odd_rows: bool = True):
         self.params = dict(params)
         self.cparams = make_params(params, storage=storage, layout_pad=layout_pad)
         self.shape = (self.cparams.nz, self.cparams.ny, self.cparams.nx)
         self.ctx = lbm_create(self.cparams, stream)
-        if block is not None or nontemporal is not None or blocks_per_cu:
+        if block is not None or nontemporal is not None or blocks_per_cu or not odd_rows:
             lbm_set_launch(self.ctx, block or 1024, True if nontemporal is None else bool(nontemporal),
-                           blocks_per_cu)
+                           blocks_per_cu, odd_rows)
 
     def init(self, Q):
         lbm_init_fields(self.ctx, np.asarray(Q, dtype=np.float64).reshape((5,) + self.shape))

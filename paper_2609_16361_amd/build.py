@@ -1,7 +1,12 @@
 """Compile the HIP library libgrlbm.so for gfx950 with hipcc (in-tree).
 
 The library holds every kernel of the solver and the C ABI of include/grlbm.h.
-Packed-FP32 instructions are disabled for all device code.
+Packed-FP32 instructions are disabled for all device code.  Multiply-adds are
+fused only inside one source expression (-ffp-contract=on): the collision is
+inlined into several kernels (the two AA parities, the row-staged odd step, the
+batched persistent kernel) and with the compiler's default cross-statement fusion
+each copy could round differently; this way every kernel computes a cell update
+with the same FP32 operations and the paths agree bit for bit.
 """
 import os
 import subprocess
@@ -15,7 +20,7 @@ ARCH = "gfx950"
 
 def hipcc_cmd(out, extra=()):
     return (["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on",
              "-Wall", "-Wno-unused-function", f"-I{os.path.join(HERE, '..', 'include')}"]
             + list(extra) + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", out])
 

@@ -110,7 +110,6 @@ using grlbm::fail;
 namespace {
 
 constexpr int kGroups = 4;  // (collision, storage) pairs
-constexpr int64_t kLdsPerCU = 160 * 1024;
 
 int group_of(const lbm_params* p) { return p->collision * 2 + (p->storage == LBM_STORE_F16 ? 1 : 0); }
 
@@ -199,7 +198,7 @@ hipError_t launch_group_t(lbm_batch* b, int g, int32_t j) {
   T* arena = reinterpret_cast<T*>(b->arena);
   const BatchTile* tiles = b->d_tiles + (size_t)g * b->max_tiles;
   const int32_t* nt = b->d_ntiles + g;
-  int lds = b->tune.blocks_per_cu > 0 ? (int)(kLdsPerCU / (b->tune.blocks_per_cu + 1)) + 256 : 0;
+  int lds = b->tune.blocks_per_cu > 0 ? (int)(grlbm::kLdsPerCU / (b->tune.blocks_per_cu + 1)) + 256 : 0;
   if (lds > 65536) lds = 65536;
   if (b->tune.nontemporal)
     hipLaunchKernelGGL((grlbm::k_batch_step<COLL, T, true>), grid, block, lds, b->stream, arena, b->d_insts, tiles,

@@ -109,8 +109,14 @@ __device__ __forceinline__ float ld(const T* p) {
   }
 }
 
+// A stored population is the FP32 result rounded to the storage type.  For FP16
+// the empty asm pins v as an FP32 register value first: otherwise the compiler may
+// fold the last multiply-add into the conversion (one rounding straight to FP16)
+// in one kernel and not in another, and kernels sharing the collision would store
+// different bits.
 template <typename T, bool NT>
 __device__ __forceinline__ void st(T* p, float v) {
+  if constexpr (sizeof(T) == 2) asm volatile("" : "+v"(v));
   if constexpr (NT) {
     __builtin_nontemporal_store(static_cast<T>(v), p);
   } else {

@@ -183,6 +183,39 @@ def test_launch_shapes_bitwise(block, nt, bpc):
     assert np.array_equal(fr, fb)
 
 
+ROW_CASES = [
+    ("300x3x2 zero-gradient x, ragged row block", (300, 3, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
+    ("64x5x4 zero-gradient all, BGK", (64, 5, 4), (1, 1, 1), inputs.BGK, None),
+    ("1024x2x2 periodic, longest staged row", (1024, 2, 2), (0, 0, 0), inputs.RLB_SENSOR, None),
+    ("1025x2x2 periodic, direct fallback", (1025, 2, 2), (0, 0, 0), inputs.RLB_SENSOR, None),
+    ("1x5x3 periodic, one-cell rows", (1, 5, 3), (0, 0, 0), inputs.RLB_SENSOR, None),
+    ("2x3x3 zero-gradient x, two-cell rows", (2, 3, 3), (1, 0, 1), inputs.RLB_SENSOR, None),
+    ("96x4x3 periodic, FP16", (96, 4, 3), (0, 0, 0), inputs.RLB_SENSOR, binding.LBM_STORE_F16),
+]
+
+
+@pytest.mark.parametrize("name,dims,bc,coll,storage", ROW_CASES)
+def test_odd_row_staging_bitwise(name, dims, bc, coll, storage):
+    """The odd step with the +-x populations shifted in LDS (one block per row) ends
+    bitwise where the direct odd step ends, diagnostics included."""
+    case = inputs.random_smooth(*dims, seed=sum(dims), amp=0.06, bc=bc, collision=coll)
+    say(f"odd row staging {name}")
+    out = []
+    for rows in (False, True):
+        with binding.Solver(case.params, storage=storage, odd_rows=rows) as s:
+            s.init(case.Q0)
+            s.step(7, 1)
+            f, st = s.populations()
+            d, status = s.diagnostics()
+            out.append((f, s.moments(), d, status))
+    (fa, Qa, da, sa), (fb, Qb, db, sb) = out
+    assert np.array_equal(fa, fb) and np.array_equal(Qa, Qb)
+    assert sa == sb == binding.LBM_OK and len(da) == len(db) == 7
+    for ra, rb in zip(da, db):
+        for key in ("Ek", "eps_s", "eps_d"):
+            assert ra[key] == pytest.approx(rb[key], rel=1e-6, abs=1e-30), key
+
+
 def test_periodic_conservation_gpu():
     """Totals of the five fields on a periodic grid: FP32 rounding only.  (The
     Mach 1.25 vortex is under-resolved on 24^3 and diverges after about 180 steps in
