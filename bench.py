@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--nontemporal", type=int, default=None)
     ap.add_argument("--layout-pad", type=int, default=0)
-    ap.add_argument("--odd-rows", type=int, default=1,
+    ap.add_argument("--odd-lds", type=int, default=1,
                     help="1: odd step shifts the +-x populations in LDS (default); 0: direct")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bw-probe", action="store_true")
@@ -292,7 +292,7 @@ def main():
     bytes_per_lup = BYTES_PER_LUP_F32 / 2 if args.fp16 else BYTES_PER_LUP_F32
     solver = binding.Solver(case.params, stream=stream.cuda_stream, block=args.block,
                             nontemporal=None if args.nontemporal is None else bool(args.nontemporal),
-                            layout_pad=args.layout_pad, storage=storage, odd_rows=bool(args.odd_rows))
+                            layout_pad=args.layout_pad, storage=storage, odd_lds=bool(args.odd_lds))
     solver.init(case.Q0)
     del case.Q0
 
@@ -343,7 +343,7 @@ def main():
                    "cells": cells, "steps": args.steps, "diag_every": args.diag_every,
                    "block": args.block or 1024,
                    "nontemporal": True if args.nontemporal is None else bool(args.nontemporal),
-                   "odd_rows": bool(args.odd_rows),
+                   "odd_lds": bool(args.odd_lds),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),

@@ -159,12 +159,12 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
  * multiple of 64 in [64, 1024]; default 1024), nontemporal loads/stores on or off
  * (default on), and an occupancy cap of `blocks_per_cu` resident blocks per compute
  * unit (1..32, enforced by reserving LDS; 0 = no cap, the default).  With
- * `odd_rows` = 1 (the default) the odd AA step of a grid with nx <= 1024 runs one
- * block per x-row and shifts the +-x populations through LDS, so that all its HBM
- * accesses are aligned; `block` and `blocks_per_cu` then apply to the even step
- * only.  Results do not depend on any of these settings.  EINVAL otherwise. */
+ * `odd_lds` = 1 (the default) the odd AA step runs over tiles of 256 consecutive
+ * cells and moves the +-x populations through LDS, so that all its HBM accesses
+ * are aligned; `block` and `blocks_per_cu` then apply to the even step only.
+ * Results do not depend on any of these settings.  EINVAL otherwise. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t nontemporal, int32_t blocks_per_cu,
-                          int32_t odd_rows);
+                          int32_t odd_lds);
 
 /* Completed steps. */
 lbm_status lbm_get_step(lbm_ctx* ctx, int64_t* step);

@@ -241,9 +241,9 @@ def lbm_set_populations(ctx: int, f: np.ndarray, step: int) -> None:
 
 
 def lbm_set_launch(ctx: int, block: int, nontemporal: bool, blocks_per_cu: int = 0,
-                   odd_rows: bool = True) -> None:
+                   odd_lds: bool = True) -> None:
     _check(load().lbm_set_launch(ctx, int(block), int(bool(nontemporal)), int(blocks_per_cu),
-                                 int(bool(odd_rows))),
+                                 int(bool(odd_lds))),
            "lbm_set_launch")
 
 
@@ -274,14 +274,14 @@ class Solver:
 
     def __init__(self, params: dict, stream: int | None = None, storage: int | None = None,
                  block: int | None = None, nontemporal: bool | None = None, layout_pad: int = 0,
-                 blocks_per_cu: int = 0, odd_rows: bool = True):
+                 blocks_per_cu: int = 0, odd_lds: bool = True):
         self.params = dict(params)
         self.cparams = make_params(params, storage=storage, layout_pad=layout_pad)
         self.shape = (self.cparams.nz, self.cparams.ny, self.cparams.nx)
         self.ctx = lbm_create(self.cparams, stream)
-        if block is not None or nontemporal is not None or blocks_per_cu or not odd_rows:
+        if block is not None or nontemporal is not None or blocks_per_cu or not odd_lds:
             lbm_set_launch(self.ctx, block or 1024, True if nontemporal is None else bool(nontemporal),
-                           blocks_per_cu, odd_rows)
+                           blocks_per_cu, odd_lds)
 
     def init(self, Q):
         lbm_init_fields(self.ctx, np.asarray(Q, dtype=np.float64).reshape((5,) + self.shape))

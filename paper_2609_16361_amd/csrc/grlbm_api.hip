@@ -213,7 +213,7 @@ struct lbm_ctx {
   int block = 1024;
   bool nt = true;
   int lds = 0;
-  bool odd_rows = true;
+  bool odd_lds = true;
   float* partials = nullptr;
   int64_t partials_blocks = 0;
   float* ring = nullptr;
@@ -225,8 +225,8 @@ struct lbm_ctx {
 namespace {
 
 lbm_status ensure_partials(lbm_ctx* c) {
-  // the row-staged odd step launches ny * nz blocks, never more than this
-  const int64_t nb = grlbm::step_blocks(c->g, c->block);
+  // partials for the larger of the two launch shapes (even step, LDS odd step)
+  const int64_t nb = std::max(grlbm::step_blocks(c->g, c->block), grlbm::odd_tiles(c->g).blocks);
   if (nb <= c->partials_blocks) return LBM_OK;
   if (c->partials) HIP_TRY(hipFree(c->partials));
   c->partials = nullptr;
@@ -329,16 +329,16 @@ lbm_status lbm_create_in(const lbm_params* p, void* dev_buf, size_t bytes, void*
 }
 
 lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t nontemporal, int32_t blocks_per_cu,
-                          int32_t odd_rows) {
+                          int32_t odd_lds) {
   if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-  if (odd_rows != 0 && odd_rows != 1) return fail(LBM_EINVAL, "odd_rows = %d must be 0 or 1", odd_rows);
+  if (odd_lds != 0 && odd_lds != 1) return fail(LBM_EINVAL, "odd_lds = %d must be 0 or 1", odd_lds);
   if (block < 64 || block > 1024 || block % 64 != 0)
     return fail(LBM_EINVAL, "block = %d must be a multiple of 64 in [64, 1024]", block);
   if (blocks_per_cu < 0 || blocks_per_cu > 32)
     return fail(LBM_EINVAL, "blocks_per_cu = %d outside [0, 32]", blocks_per_cu);
   c->block = block;
   c->nt = nontemporal != 0;
-  c->odd_rows = odd_rows != 0;
+  c->odd_lds = odd_lds != 0;
   // reserve just over 1/(blocks_per_cu + 1) of the 160 KB LDS of a CU per block
   c->lds = blocks_per_cu > 0 ? (int)(grlbm::kLdsPerCU / (blocks_per_cu + 1)) + 256 : 0;
   if (c->lds > 65536) c->lds = 65536;
@@ -389,7 +389,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n, int32_t diag_every) {
   L.f16 = c->p.storage == LBM_STORE_F16;
   L.nt = c->nt;
   L.lds = c->lds;
-  L.odd_rows = c->odd_rows;
+  L.odd_lds = c->odd_lds;
   L.partials = nullptr;
   if (diag_every > 0) {
     lbm_status st = ensure_partials(c);

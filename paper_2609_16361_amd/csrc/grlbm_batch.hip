@@ -65,32 +65,38 @@ __global__ void __launch_bounds__(1024) k_batch_step(T* __restrict__ arena, cons
                                                       const BatchTile* __restrict__ tiles,
                                                       const int32_t* __restrict__ ntiles,
                                                       const int64_t* __restrict__ clock, int32_t j) {
+  extern __shared__ float xs[];  // x slots of an odd-step tile (tile_update_odd)
   const int32_t nt = *ntiles;
   const int64_t t = *clock + j;
   for (int32_t tile = blockIdx.x; tile < nt; tile += gridDim.x) {
     const BatchTile bt = tiles[tile];
     const BatchInst* I = insts + bt.inst;
     const int64_t ts = I->t_start;
-    if (t < ts || t >= I->t_end) continue;
-    const int n = bt.tile * (int)blockDim.x + (int)threadIdx.x;
-    if (n >= I->cells) continue;
+    if (t < ts || t >= I->t_end) continue;  // the same for the whole block
+    const int n0 = bt.tile * (int)blockDim.x;
+    const int n = n0 + (int)threadIdx.x;
+    const bool act = n < I->cells;
     const Grid g = I->g;
-    int x, y;
-    const int row = div_exact(n, g.nx, I->inv_nx, x);
-    const int z = div_exact(row, g.ny, I->inv_ny, y);
+    int x = 0, y = 0, z = 0;
+    if (act) {
+      const int row = div_exact(n, g.nx, I->inv_nx, x);
+      z = div_exact(row, g.ny, I->inv_ny, y);
+    }
     const Coll c = I->c;
     T* F = arena + I->off;
-    // the same instantiation as a single context uses for this instance, so the
-    // arithmetic (and its FMA contraction) is identical and so are the results
+    // the same arithmetic as a single context uses for this instance, so the
+    // results are bitwise the same
     const bool odd = ((t - ts) & 1) != 0;
-    if (g.zg_x | g.zg_y | g.zg_z) {
-      if (odd)
-        cell_update<true, COLL, T, true, false, NT>(F, g, c, x, y, z, nullptr);
+    const bool zg = g.zg_x | g.zg_y | g.zg_z;
+    if (odd) {
+      // every lane takes part (barriers inside)
+      if (zg)
+        tile_update_odd<COLL, T, true, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr);
       else
+        tile_update_odd<COLL, T, false, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr);
+    } else if (act) {
+      if (zg)
         cell_update<false, COLL, T, true, false, NT>(F, g, c, x, y, z, nullptr);
-    } else {
-      if (odd)
-        cell_update<true, COLL, T, false, false, NT>(F, g, c, x, y, z, nullptr);
       else
         cell_update<false, COLL, T, false, false, NT>(F, g, c, x, y, z, nullptr);
     }
@@ -200,6 +206,8 @@ hipError_t launch_group_t(lbm_batch* b, int g, int32_t j) {
   const int32_t* nt = b->d_ntiles + g;
   int lds = b->tune.blocks_per_cu > 0 ? (int)(grlbm::kLdsPerCU / (b->tune.blocks_per_cu + 1)) + 256 : 0;
   if (lds > 65536) lds = 65536;
+  const int need = 15 * (int)sizeof(float) * b->tune.block;  // odd-step x slots of one tile
+  if (lds < need) lds = need;
   if (b->tune.nontemporal)
     hipLaunchKernelGGL((grlbm::k_batch_step<COLL, T, true>), grid, block, lds, b->stream, arena, b->d_insts, tiles,
                        nt, b->d_clock, j);

@@ -403,4 +403,139 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
   }
 }
 
+// ----------------------------------------------------- odd update of one tile
+// The odd half step of a tile of B = blockDim.x consecutive cells [n0, n0 + B) of
+// one grid (the tile may start mid-row and span rows), with the +-x populations
+// moved through LDS.  Read directly, the x populations sit one element off the
+// 64-lane chunks, so every wave would touch one more cache line than it moves and
+// leave partial lines behind.  Here the two x slots of the tile's own cells are
+// loaded aligned into LDS, the shifted reads and writes happen in LDS, and the
+// slots go back to HBM aligned; the y, z and rest populations are accessed
+// directly as in cell_update.
+//
+// In the AA scheme every slot location is read and then written by one and the
+// same cell: slot 1 of cell m by its left neighbour (by m itself when m sits on a
+// zero-gradient x = 0 face), slot 2 of m by its right neighbour (by m itself on an
+// x = nx - 1 face).  A location whose cell lies in the tile is staged; the few
+// whose cell lies in another tile (the tile's ends, periodic wraps to a row end
+// outside the tile) are accessed directly by that cell, and the tile does not write
+// them back.  So tiles never touch each other's locations and need no ordering.
+//
+// Every lane of the block must call this (it holds two barriers); lanes with
+// act = false (past the grid's last cell) only take part in the barriers.  xs has
+// room for 15 * B floats: the two slots and a per-lane column that absorbs the LDS
+// writes a cell does not make, so that no LDS access needs a branch.  EDGES =
+// false asserts that the tile holds whole x-rows (then every x location is in the
+// tile and the edge handling compiles away).  The collision is the same call as in
+// cell_update, so the results are bitwise those of cell_update<true, ...>.
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool EDGES = true>
+__device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g, const Coll& c, int n0,
+                                                bool act, int x, int y, int z, float* xs, float* vals) {
+  const int B = blockDim.x;
+  const int lane = threadIdx.x;
+  const Nbr b = make_nbr(g, x, y, z);
+  const int64_t S = g.S;
+  float* s1 = xs;              // slot 1 of the tile's cells, [field][B]
+  float* s2 = xs + 5 * B;      // slot 2
+  float* sink = xs + 10 * B;   // [field][B], written and never read
+  float f[kPop];
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      const T* Fk = F + (int64_t)(7 * k) * S;
+      s1[k * B + lane] = ld<T, NT>(Fk + 1 * S + b.n);
+      s2[k * B + lane] = ld<T, NT>(Fk + 2 * S + b.n);
+      f[7 * k + 0] = ld<T, NT>(Fk + b.n);
+#pragma unroll
+      for (int i = 3; i < kQ; ++i) f[7 * k + i] = ld<T, NT>(Fk + odd_src<ZG>(g, b, i));
+    }
+  }
+  const bool lo = ZG && b.lo_x;
+  const bool hi = ZG && b.hi_x;
+  // f_{+x} lives in slot 1 of the cell itself (zero-gradient face) or in slot 2 of
+  // the left neighbour; f_{-x} in slot 2 of the cell itself or slot 1 of the right one
+  const int m1 = lo ? b.n : b.xm;
+  const int m2 = hi ? b.n : b.xp;
+  const bool in1 = !EDGES || (unsigned)(m1 - n0) < (unsigned)B;  // always true when lo
+  const bool in2 = !EDGES || (unsigned)(m2 - n0) < (unsigned)B;  // always true when hi
+  // outside the tile (so neither lo nor hi): slot 2 of m1, slot 1 of m2, directly
+  float d1[kFields], d2[kFields];
+  if (act && !in1) {
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) d1[k] = ld<T, NT>(F + (int64_t)(7 * k + 2) * S + m1);
+  }
+  if (act && !in2) {
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) d2[k] = ld<T, NT>(F + (int64_t)(7 * k + 1) * S + m2);
+  }
+  __syncthreads();
+  const float* r1 = (lo ? s1 : s2) + (in1 ? m1 - n0 : lane);
+  const float* r2 = (hi ? s2 : s1) + (in2 ? m2 - n0 : lane);
+  // LDS targets of the post-collision f_{+x}: slot 1 of the right neighbour, and
+  // (ghost copy) slot 1 of the cell itself on an x = 0 face; f_{-x} mirrored
+  float* w1 = (!hi && in2) ? s1 + (b.xp - n0) : sink + lane;
+  float* w1g = lo ? s1 + lane : sink + lane;
+  float* w2 = (!lo && in1) ? s2 + (b.xm - n0) : sink + lane;
+  float* w2g = hi ? s2 + lane : sink + lane;
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      const float v1 = r1[k * B];
+      const float v2 = r2[k * B];
+      f[7 * k + 1] = in1 ? v1 : d1[k];
+      f[7 * k + 2] = in2 ? v2 : d2[k];
+    }
+    CellDiag d;
+    collide<COLL, DIAG, sizeof(T) == 2>(f, c, &d);
+    if constexpr (DIAG) {
+      vals[0] = d.ek;
+      vals[1] = d.eps_s;
+      vals[2] = d.eps_d;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) vals[3 + k] = d.dq[k];
+      vals[8] = d.nonfinite;
+    }
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      T* Fk = F + (int64_t)(7 * k) * S;
+      const float* fo = f + 7 * k;
+      st<T, NT>(Fk + b.n, fo[0]);
+      if (!(ZG && b.hi_y)) st<T, NT>(Fk + 3 * S + b.yp, fo[3]);
+      if (!(ZG && b.lo_y)) st<T, NT>(Fk + 4 * S + b.ym, fo[4]);
+      if (!(ZG && b.hi_z)) st<T, NT>(Fk + 5 * S + b.zp, fo[5]);
+      if (!(ZG && b.lo_z)) st<T, NT>(Fk + 6 * S + b.zm, fo[6]);
+      if constexpr (ZG) {
+        if (b.lo_y) st<T, NT>(Fk + 3 * S + b.n, fo[3]);
+        if (b.hi_y) st<T, NT>(Fk + 4 * S + b.n, fo[4]);
+        if (b.lo_z) st<T, NT>(Fk + 5 * S + b.n, fo[5]);
+        if (b.hi_z) st<T, NT>(Fk + 6 * S + b.n, fo[6]);
+      }
+      w1[k * B] = fo[1];
+      w2[k * B] = fo[2];
+      if constexpr (ZG) {
+        w1g[k * B] = fo[1];
+        w2g[k * B] = fo[2];
+      }
+    }
+    if (!hi && !in2) {
+#pragma unroll
+      for (int k = 0; k < kFields; ++k) st<T, NT>(F + (int64_t)(7 * k + 1) * S + b.xp, f[7 * k + 1]);
+    }
+    if (!lo && !in1) {
+#pragma unroll
+      for (int k = 0; k < kFields; ++k) st<T, NT>(F + (int64_t)(7 * k + 2) * S + b.xm, f[7 * k + 2]);
+    }
+  }
+  __syncthreads();
+  // write back the slots of this tile's cells whose reader/writer is in the tile
+  if (act && in1) {
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) st<T, NT>(F + (int64_t)(7 * k + 1) * S + b.n, s1[k * B + lane]);
+  }
+  if (act && in2) {
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) st<T, NT>(F + (int64_t)(7 * k + 2) * S + b.n, s2[k * B + lane]);
+  }
+}
+
 }  // namespace grlbm

@@ -35,17 +35,22 @@ struct StepLaunch {
   bool diag;         // fused diagnostics
   bool nt;           // nontemporal loads and stores
   int lds;           // dynamic LDS bytes reserved per block (occupancy cap), 0 = none
-  bool odd_rows;     // odd steps with nx <= kMaxRowBlock use k_step_odd_rows
+  bool odd_lds;      // odd steps use k_step_odd_tiles (x populations shifted in LDS)
 };
 
 constexpr int64_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
-constexpr int kMaxRowBlock = 1024;         // longest x-row of the row-staged odd step
+constexpr int kOddTile = 256;              // cells per linear tile of k_step_odd_tiles
+constexpr int kMaxRowTile = 1024;          // longest x-row k_step_odd_tiles maps to one block
 
 hipError_t launch_step(const StepLaunch& L, hipStream_t s);
 int64_t step_blocks(const Grid& g, int block);
-bool row_staged(const StepLaunch& L);   // this launch uses k_step_odd_rows
-int row_block(const Grid& g);           // its block size (nx rounded up to 64)
-int row_lds(const Grid& g);             // its dynamic LDS bytes
+struct OddTiles {
+  bool rows;       // one block per x-row, else linear tiles of kOddTile cells
+  int block;       // threads per block
+  int64_t blocks;  // blocks (= diagnostic partials)
+  int lds;         // dynamic LDS bytes per block
+};
+OddTiles odd_tiles(const Grid& g);          // launch shape of k_step_odd_tiles
 int64_t launch_blocks(const StepLaunch& L);  // blocks (= diagnostic partials) of a launch
 hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s);
 hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const double* Q, int64_t N,

@@ -4,8 +4,8 @@
 //               parity): 35 loads, the collision of Algorithm 1 in registers, 35
 //               stores; optional fused diagnostics (wavefront shuffle + LDS
 //               reduction to one partial per block)
-//   k_step_odd_rows  the odd half step with one block per x-row: the +-x
-//               populations are shifted in LDS so every HBM access stays aligned
+//   k_step_odd_tiles  the odd half step over linear tiles of cells with the +-x
+//               populations shifted in LDS, so every HBM access stays aligned
 //   k_finalize  deterministic reduction of the per-block partials into one record
 //   k_init      equilibrium populations from the conserved fields
 //   k_gather    parity-aware readout: canonical populations or conserved moments
@@ -83,102 +83,41 @@ __global__ void __launch_bounds__(1024) k_step(T* __restrict__ F, Grid g, Coll c
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
-// Odd AA step with one block per x-row (blockDim.x = nx rounded up to 64, at most
-// 1024).  In the odd half step f_{+-x} are read from slots 2/1 of the x-1/x+1
-// neighbours and written to slots 1/2 of the x+1/x-1 neighbours: addressed straight
-// in HBM those accesses are shifted by one element against the 64-element wave
-// chunks, so every wave touches one more 128-byte line than it moves.  Here the two
-// x slots of the whole row are loaded aligned into LDS, shifted there, and stored
-// back aligned after the collision; the y and z populations and the rest population
-// go straight to HBM as in k_step.  The arithmetic is cell_update's, so the result
-// is bitwise the same as k_step's odd step.
-template <int COLL, typename T, bool ZG, bool DIAG, bool NT>
-__global__ void __launch_bounds__(1024) k_step_odd_rows(T* __restrict__ F, Grid g, Coll c,
-                                                         float* __restrict__ partials) {
-  extern __shared__ float xrow[];  // [slot 1 | slot 2][field][blockDim.x]
-  const int bs = blockDim.x;
-  const int x = threadIdx.x;
-  const int row = blockIdx.x;
-  const bool act = x < g.nx;
-  const int nx = g.nx;
-  const Nbr b = make_nbr(g, act ? x : 0, row % g.ny, row / g.ny);
-  const int64_t S = g.S;
-  float* s1 = xrow;            // slot 1 (+x population arriving from the left)
-  float* s2 = xrow + 5 * bs;   // slot 2 (-x population arriving from the right)
-  float f[kPop];
-  if (act) {
-#pragma unroll
-    for (int k = 0; k < kFields; ++k) {
-      const T* Fk = F + (int64_t)(7 * k) * S;
-      s1[k * bs + x] = ld<T, NT>(Fk + 1 * S + b.n);
-      s2[k * bs + x] = ld<T, NT>(Fk + 2 * S + b.n);
-      f[7 * k + 0] = ld<T, NT>(Fk + b.n);
-#pragma unroll
-      for (int i = 3; i < kQ; ++i) f[7 * k + i] = ld<T, NT>(Fk + odd_src<ZG>(g, b, i));
+// Odd AA step over tiles of consecutive cells with the +-x populations shifted in
+// LDS (tile_update_odd): every HBM access of the x slots is aligned.  ROWS: one
+// block per x-row (nx <= 1024, blockDim.x = nx rounded up to 64); otherwise linear
+// tiles of blockDim.x cells that may start mid-row.  Bitwise the same result as
+// k_step's odd step.
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool ROWS>
+__global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid g, Coll c,
+                                                          float* __restrict__ partials) {
+  extern __shared__ float xs[];
+  int n0, x = 0, y = 0, z = 0;
+  bool act;
+  if constexpr (ROWS) {
+    const int row = (int)blockIdx.x;
+    n0 = row * g.nx;
+    act = (int)threadIdx.x < g.nx;
+    z = row / g.ny;
+    y = row - z * g.ny;
+    if (act) x = (int)threadIdx.x;
+  } else {
+    n0 = (int)blockIdx.x * (int)blockDim.x;
+    const int n = n0 + (int)threadIdx.x;
+    act = n < g.nx * g.ny * g.nz;
+    if (act) {
+      const int row = n / g.nx;
+      x = n - row * g.nx;
+      z = row / g.ny;
+      y = row - z * g.ny;
     }
   }
-  __syncthreads();
-  // periodic neighbours inside the row (the same wrap as make_nbr's xm / xp)
-  const int xm = (x == 0) ? nx - 1 : x - 1;
-  const int xp = (x == nx - 1) ? 0 : x + 1;
-  const bool lo = ZG && b.lo_x;
-  const bool hi = ZG && b.hi_x;
-  if (act) {
-#pragma unroll
-    for (int k = 0; k < kFields; ++k) {
-      f[7 * k + 1] = lo ? s1[k * bs + x] : s2[k * bs + xm];
-      f[7 * k + 2] = hi ? s2[k * bs + x] : s1[k * bs + xp];
-    }
-  }
-  __syncthreads();
   float vals[kDiagVals];
   if constexpr (DIAG) {
 #pragma unroll
     for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
   }
-  if (act) {
-    CellDiag d;
-    collide<COLL, DIAG, sizeof(T) == 2>(f, c, &d);
-    if constexpr (DIAG) {
-      vals[0] = d.ek;
-      vals[1] = d.eps_s;
-      vals[2] = d.eps_d;
-#pragma unroll
-      for (int k = 0; k < 5; ++k) vals[3 + k] = d.dq[k];
-      vals[8] = d.nonfinite;
-    }
-#pragma unroll
-    for (int k = 0; k < kFields; ++k) {
-      T* Fk = F + (int64_t)(7 * k) * S;
-      const float* fo = f + 7 * k;
-      st<T, NT>(Fk + b.n, fo[0]);
-      if (!(ZG && b.hi_y)) st<T, NT>(Fk + 3 * S + b.yp, fo[3]);
-      if (!(ZG && b.lo_y)) st<T, NT>(Fk + 4 * S + b.ym, fo[4]);
-      if (!(ZG && b.hi_z)) st<T, NT>(Fk + 5 * S + b.zp, fo[5]);
-      if (!(ZG && b.lo_z)) st<T, NT>(Fk + 6 * S + b.zm, fo[6]);
-      if constexpr (ZG) {
-        if (b.lo_y) st<T, NT>(Fk + 3 * S + b.n, fo[3]);
-        if (b.hi_y) st<T, NT>(Fk + 4 * S + b.n, fo[4]);
-        if (b.lo_z) st<T, NT>(Fk + 5 * S + b.n, fo[5]);
-        if (b.hi_z) st<T, NT>(Fk + 6 * S + b.n, fo[6]);
-      }
-      // every slot of the row receives exactly one value: from the upstream
-      // neighbour, or on a zero-gradient face the ghost copy of the cell itself
-      if (!hi) s1[k * bs + xp] = fo[1];
-      if (lo) s1[k * bs + x] = fo[1];
-      if (!lo) s2[k * bs + xm] = fo[2];
-      if (hi) s2[k * bs + x] = fo[2];
-    }
-  }
-  __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int k = 0; k < kFields; ++k) {
-      T* Fk = F + (int64_t)(7 * k) * S;
-      st<T, NT>(Fk + 1 * S + b.n, s1[k * bs + x]);
-      st<T, NT>(Fk + 2 * S + b.n, s2[k * bs + x]);
-    }
-  }
+  tile_update_odd<COLL, T, ZG, DIAG, NT, !ROWS>(F, g, c, n0, act, x, y, z, xs, vals);
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
@@ -337,16 +276,23 @@ template <bool ODD, int COLL, typename T, bool ZG, bool DIAG>
 static hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
   const Grid& g = L.g;
   T* F = (T*)L.F;
-  if (ODD && row_staged(L)) {
-    const int xb = row_block(g);
-    const unsigned rows = (unsigned)((int64_t)g.ny * g.nz);
-    const int lds = row_lds(g);
-    if (L.nt)
-      hipLaunchKernelGGL((k_step_odd_rows<COLL, T, ZG, DIAG, true>), dim3(rows), dim3(xb), lds, s, F, g, L.c,
-                         L.partials);
-    else
-      hipLaunchKernelGGL((k_step_odd_rows<COLL, T, ZG, DIAG, false>), dim3(rows), dim3(xb), lds, s, F, g, L.c,
-                         L.partials);
+  if (ODD && L.odd_lds) {
+    const OddTiles ot = odd_tiles(g);
+    if (ot.rows) {
+      if (L.nt)
+        hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, true, true>), dim3((unsigned)ot.blocks),
+                           dim3(ot.block), ot.lds, s, F, g, L.c, L.partials);
+      else
+        hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, false, true>), dim3((unsigned)ot.blocks),
+                           dim3(ot.block), ot.lds, s, F, g, L.c, L.partials);
+    } else {
+      if (L.nt)
+        hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, true, false>), dim3((unsigned)ot.blocks),
+                           dim3(ot.block), ot.lds, s, F, g, L.c, L.partials);
+      else
+        hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, false, false>), dim3((unsigned)ot.blocks),
+                           dim3(ot.block), ot.lds, s, F, g, L.c, L.partials);
+    }
     return hipGetLastError();
   }
   const int64_t blocks = step_blocks(g, L.block);
@@ -383,24 +329,26 @@ int64_t step_blocks(const Grid& g, int block) {
   return (int64_t)((g.nx + block - 1) / block) * g.ny * g.nz;
 }
 
-bool row_staged(const StepLaunch& L) { return L.odd && L.odd_rows && L.g.nx <= kMaxRowBlock; }
-
-int row_block(const Grid& g) { return (g.nx + 63) / 64 * 64; }
-
-// LDS per row block: the two x slots of the row (10 floats per cell), padded so
-// that about 16 waves are resident per CU (1024 / row_block blocks), which is where
-// the odd step's sustained bandwidth peaks; at most 64 KiB.
-int row_lds(const Grid& g) {
-  const int xb = row_block(g);
-  const int need = 10 * (int)sizeof(float) * xb;
-  const int per_cu = 1024 / xb > 1 ? 1024 / xb : 1;
+// Launch shape of k_step_odd_tiles: one block per x-row when a row fits in a block
+// (no index division, no tile edge inside a row), else linear tiles of kOddTile
+// cells.  The dynamic LDS holds the two x slots of a tile and a sink column (15
+// floats per cell), padded so that about 16 waves are resident per CU, where the
+// odd step's sustained bandwidth peaks.
+OddTiles odd_tiles(const Grid& g) {
+  OddTiles t;
+  t.rows = g.nx <= kMaxRowTile;
+  t.block = t.rows ? (g.nx + 63) / 64 * 64 : kOddTile;
+  t.blocks = t.rows ? (int64_t)g.ny * g.nz : ((int64_t)g.nx * g.ny * g.nz + kOddTile - 1) / kOddTile;
+  const int need = 15 * (int)sizeof(float) * t.block;
+  const int per_cu = 1024 / t.block > 1 ? 1024 / t.block : 1;
   int lds = (int)(kLdsPerCU / (per_cu + 1)) + 256;
   if (lds > 65536) lds = 65536;
-  return lds > need ? lds : need;
+  t.lds = lds > need ? lds : need;
+  return t;
 }
 
 int64_t launch_blocks(const StepLaunch& L) {
-  return row_staged(L) ? (int64_t)L.g.ny * L.g.nz : step_blocks(L.g, L.block);
+  return L.odd && L.odd_lds ? odd_tiles(L.g).blocks : step_blocks(L.g, L.block);
 }
 
 hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s) {

@@ -183,26 +183,31 @@ def test_launch_shapes_bitwise(block, nt, bpc):
     assert np.array_equal(fr, fb)
 
 
-ROW_CASES = [
-    ("300x3x2 zero-gradient x, ragged row block", (300, 3, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
+ODD_LDS_CASES = [
+    ("300x3x2 zero-gradient x, tiles span rows", (300, 3, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
+    ("100x5x3 periodic, wraps in and out of tiles", (100, 5, 3), (0, 0, 0), inputs.RLB_SENSOR, None),
     ("64x5x4 zero-gradient all, BGK", (64, 5, 4), (1, 1, 1), inputs.BGK, None),
-    ("1024x2x2 periodic, longest staged row", (1024, 2, 2), (0, 0, 0), inputs.RLB_SENSOR, None),
-    ("1025x2x2 periodic, direct fallback", (1025, 2, 2), (0, 0, 0), inputs.RLB_SENSOR, None),
+    ("1025x2x2 periodic, rows longer than tiles", (1025, 2, 2), (0, 0, 0), inputs.RLB_SENSOR, None),
     ("1x5x3 periodic, one-cell rows", (1, 5, 3), (0, 0, 0), inputs.RLB_SENSOR, None),
-    ("2x3x3 zero-gradient x, two-cell rows", (2, 3, 3), (1, 0, 1), inputs.RLB_SENSOR, None),
+    ("2x3x3 zero-gradient x z, two-cell rows", (2, 3, 3), (1, 0, 1), inputs.RLB_SENSOR, None),
+    ("7x1x1 periodic, one partial tile", (7, 1, 1), (0, 0, 0), inputs.RLB_SENSOR, None),
     ("96x4x3 periodic, FP16", (96, 4, 3), (0, 0, 0), inputs.RLB_SENSOR, binding.LBM_STORE_F16),
+    ("257x3x2 zero-gradient x, FP16 BGK", (257, 3, 2), (1, 0, 0), inputs.BGK, binding.LBM_STORE_F16),
+    ("1500x2x2 zero-gradient x, linear tiles", (1500, 2, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
+    ("1100x3x1 periodic FP16, linear tiles", (1100, 3, 1), (0, 0, 0), inputs.RLB_SENSOR, binding.LBM_STORE_F16),
 ]
 
 
-@pytest.mark.parametrize("name,dims,bc,coll,storage", ROW_CASES)
-def test_odd_row_staging_bitwise(name, dims, bc, coll, storage):
-    """The odd step with the +-x populations shifted in LDS (one block per row) ends
-    bitwise where the direct odd step ends, diagnostics included."""
+@pytest.mark.parametrize("name,dims,bc,coll,storage", ODD_LDS_CASES)
+def test_odd_lds_tiles_bitwise(name, dims, bc, coll, storage):
+    """The odd step over tiles of consecutive cells with the +-x populations moved
+    through LDS (one block per row up to nx = 1024, linear 256-cell tiles beyond)
+    ends bitwise where the direct odd step ends, diagnostics included."""
     case = inputs.random_smooth(*dims, seed=sum(dims), amp=0.06, bc=bc, collision=coll)
-    say(f"odd row staging {name}")
+    say(f"odd step via LDS {name}")
     out = []
-    for rows in (False, True):
-        with binding.Solver(case.params, storage=storage, odd_rows=rows) as s:
+    for staged in (False, True):
+        with binding.Solver(case.params, storage=storage, odd_lds=staged) as s:
             s.init(case.Q0)
             s.step(7, 1)
             f, st = s.populations()
