@@ -280,7 +280,8 @@ class Solver:
         self.shape = (self.cparams.nz, self.cparams.ny, self.cparams.nx)
         self.ctx = lbm_create(self.cparams, stream)
         if block is not None or nontemporal is not None or blocks_per_cu or not odd_lds:
-            lbm_set_launch(self.ctx, block or 1024, True if nontemporal is None else bool(nontemporal),
+            default_block = 256 if self.cparams.storage == LBM_STORE_F16 else 1024
+            lbm_set_launch(self.ctx, block or default_block, True if nontemporal is None else bool(nontemporal),
                            blocks_per_cu, odd_lds)
 
     def init(self, Q):
