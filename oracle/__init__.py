@@ -60,6 +60,11 @@ class OraCellInfo(ctypes.Structure):
     ]
 
 
+class OraMms(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("rho0", "U", "P0", "a", "K", "W", "gamma", "mu", "kappa")]
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -76,6 +81,11 @@ def _load():
     lib.ora_step.argtypes = [P(OraParams), dp, dp, dp]
     lib.ora_run.argtypes = [P(OraParams), dp, dp, ctypes.c_int64, ctypes.c_int64, dp]
     lib.ora_run.restype = ctypes.c_int64
+    lib.ora_step_src.argtypes = [P(OraParams), dp, dp, dp, dp]
+    lib.ora_mms_source.argtypes = [P(OraParams), P(OraMms), ctypes.c_double, dp]
+    lib.ora_run_mms.argtypes = [P(OraParams), P(OraMms), dp, dp, dp, ctypes.c_int64, ctypes.c_double,
+                                ctypes.c_double]
+    lib.ora_mms_size.restype = ctypes.c_int32
     lib.ora_cell_info_size.restype = ctypes.c_int32
     lib.ora_params_size.restype = ctypes.c_int32
     lib.ora_num_threads.restype = ctypes.c_int32
@@ -83,6 +93,8 @@ def _load():
         raise RuntimeError("oracle cell-info layout mismatch")
     if lib.ora_params_size() != ctypes.sizeof(OraParams):
         raise RuntimeError("oracle params layout mismatch")
+    if lib.ora_mms_size() != ctypes.sizeof(OraMms):
+        raise RuntimeError("oracle manufactured-solution layout mismatch")
     _lib = lib
     return lib
 
@@ -185,3 +197,51 @@ def run(p: dict, f, nsteps: int, diag_every: int = 0):
 def num_threads() -> int:
     """Threads the oracle's parallel cell loop uses (OpenMP)."""
     return int(_load().ora_num_threads())
+
+
+def _mms(m: dict) -> OraMms:
+    o = OraMms()
+    for name, _ in OraMms._fields_:
+        setattr(o, name, float(m[name]))
+    return o
+
+
+def step_source(p: dict, f, S):
+    """One step from f[35][N] with the source S[5][N] (lattice units per step) added
+    as w_i S_k after the collision; returns (f_new, diag[9])."""
+    lib = _load()
+    P = make_params(p)
+    N = cells(p)
+    fi = np.ascontiguousarray(np.asarray(f, dtype=np.float64).reshape(35, N))
+    src = np.ascontiguousarray(np.asarray(S, dtype=np.float64).reshape(5, N))
+    fo = np.zeros_like(fi)
+    d = np.zeros(9)
+    lib.ora_step_src(ctypes.byref(P), _ptr(fi), _ptr(fo), _ptr(d), _ptr(src))
+    return fo, d
+
+
+def mms_source(p: dict, m: dict, t: float) -> np.ndarray:
+    """Source of the manufactured solution (eq. 8) at every cell at lattice time t:
+    S[5][nz][ny][nx].  m holds rho0, U, P0, a, K, W, gamma, mu, kappa in lattice
+    units."""
+    lib = _load()
+    P = make_params(p)
+    M = _mms(m)
+    S = np.zeros((5, cells(p)))
+    lib.ora_mms_source(ctypes.byref(P), ctypes.byref(M), float(t), _ptr(S))
+    return S.reshape(5, int(p["nz"]), int(p["ny"]), int(p["nx"]))
+
+
+def run_mms(p: dict, m: dict, f, nsteps: int, t0: float = 0.0, t_frac: float = 0.5):
+    """nsteps steps from f (copied) with the manufactured source; the source of step
+    s is evaluated at lattice time t0 + s + t_frac."""
+    lib = _load()
+    P = make_params(p)
+    M = _mms(m)
+    N = cells(p)
+    a = np.array(np.asarray(f, dtype=np.float64).reshape(35, N), copy=True, order="C")
+    w = np.empty_like(a)
+    S = np.empty((5, N))
+    lib.ora_run_mms(ctypes.byref(P), ctypes.byref(M), _ptr(a), _ptr(w), _ptr(S), int(nsteps), float(t0),
+                    float(t_frac))
+    return a

@@ -23,6 +23,10 @@
  *   8. Newtonian stress and Fourier flux (eq. 2), full flux Phi in the equilibrium
  *   9. regularized collision with reduced rate omega_h, or BGK (Sec. 2.2, 2.5)
  *  10. exact on-lattice push streaming into a second buffer
+ * With a source S of eq. 1 (ora_step_src) the post-collision populations gain
+ * w_i S_k before streaming (Algorithm 1, last line).  ora_mms_source writes the
+ * source of the manufactured solution of Sec. 3.1 (eq. 8), derived by hand from
+ * eq. 2 with constant mu and kappa.
  *
  * Lattice: D3Q7 with c_s^2 = 1/4 (Sec. 2.2).  The paper gives only c_s^2; the weights
  * w_0 = 1/4, w_1..6 = 1/8 are the unique nearest-neighbour isotropic set with that
@@ -39,7 +43,9 @@
  * Pins: tests/test_oracle_*.py check this file against closed forms, invariants and
  * exact solutions (lattice moment identities, finite-difference Jacobian of the
  * diffusive flux, exact recovery of prescribed gradients, conservation, exact Sod
- * Riemann solution, Becker closed form, viscous decay of a Taylor-Green vortex).
+ * Riemann solution, Becker closed form, viscous decay of a Taylor-Green vortex,
+ * second-order convergence to the manufactured solution of eq. 8, whose source is
+ * checked against a symbolic differentiation of eq. 2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -377,6 +383,12 @@ void ora_moments(const ora_params* P, const double* f, double* Q) {
     }
 }
 
+/* One collide-and-stream step with a source, as ora_step below; S (may be NULL) is
+ * the source of eq. 1 for this step in lattice units, S[5][N], projected onto the
+ * lattice weights and added to the post-collision populations (Algorithm 1, last
+ * line): f*_ki += w_i S_k. */
+void ora_step_src(const ora_params* P, const double* f_in, double* f_out, double* diag, const double* S);
+
 /* One collide-and-stream step, two buffers, push streaming:
  *   f_out(x + c_i, i) <- f*(x, i)
  * On a zero-gradient axis the population leaving the domain is dropped and the one
@@ -385,6 +397,10 @@ void ora_moments(const ora_params* P, const double* f, double* Q) {
  * kinetic energy, solenoidal and dilatational dissipation densities, the five
  * conserved totals, and the count of cells with non-finite output. */
 void ora_step(const ora_params* P, const double* f_in, double* f_out, double* diag) {
+  ora_step_src(P, f_in, f_out, diag, NULL);
+}
+
+void ora_step_src(const ora_params* P, const double* f_in, double* f_out, double* diag, const double* S) {
   const int nx = P->nx, ny = P->ny, nz = P->nz;
   const int64_t N = ora_cells(P);
   double ek = 0, es = 0, ed = 0, tot[5] = {0, 0, 0, 0, 0}, nonf = 0;
@@ -397,6 +413,10 @@ void ora_step(const ora_params* P, const double* f_in, double* f_out, double* di
         ora_cell_info info;
         for (int s = 0; s < 35; ++s) fi[s] = f_in[s * N + n];
         ora_collide(P, fi, fo, &info);
+        if (S) {
+          for (int k = 0; k < 5; ++k)
+            for (int i = 0; i < 7; ++i) fo[7 * k + i] += ORA_W[i] * S[k * N + n];
+        }
         ek += info.ek;
         es += info.eps_s;
         ed += info.eps_d;
@@ -467,3 +487,162 @@ int32_t ora_num_threads(void) {
 /* Size of the per-cell info record (lets the Python side check its mirror). */
 int32_t ora_cell_info_size(void) { return (int32_t)sizeof(ora_cell_info); }
 int32_t ora_params_size(void) { return (int32_t)sizeof(ora_params); }
+
+/* ------------------------------------------------- manufactured solution (eq. 8) */
+/* The manufactured field of Sec. 3.1 in lattice units on an n^3 periodic lattice
+ * (cell (i, j, l) at x = (i, j, l), one period per n cells): every primitive is a
+ * constant plus a sum of terms  A f(K x_axis + phase + s W t)  with f = sin or cos,
+ * K = 2 pi / n per cell and W the angular frequency per step.  The amplitudes and
+ * phases are those of eq. 8; the velocity scale U, pressure scale P0 and background
+ * density rho0 come in lattice units. */
+typedef struct {
+  double rho0, U, P0, a;  /* background density, velocity scale (c_s of eq. 8), p0, a */
+  double K, W;            /* 2 pi / n per cell, 2 pi per period in steps              */
+  double gamma, mu, kappa;/* constant viscosity and conductivity, lattice units       */
+} ora_mms;
+
+typedef struct {
+  double v, t, g[3], h[3][3]; /* value, d/dt, gradient, Hessian                        */
+} ora_jet;
+
+/* adds A f(K x_axis + ph + s W t), f = sin (is_sin) or cos, and its derivatives */
+static void ora_jet_term(ora_jet* J, const ora_mms* M, double A, int axis, double ph, double s,
+                         int is_sin, const double x[3], double t) {
+  const double arg = M->K * x[axis] + ph + s * M->W * t;
+  const double sn = sin(arg), cs = cos(arg);
+  const double f = is_sin ? sn : cs;
+  const double df = is_sin ? cs : -sn;  /* derivative of f with respect to its argument */
+  J->v += A * f;
+  J->g[axis] += A * M->K * df;
+  J->t += A * s * M->W * df;
+  J->h[axis][axis] += -A * M->K * M->K * f;
+}
+
+/* rho, u_x, u_y, u_z, p of eq. 8 with their derivatives at lattice point x, time t */
+static void ora_mms_primitives(const ora_mms* M, const double x[3], double t, ora_jet J[5]) {
+  memset(J, 0, 5 * sizeof(ora_jet));
+  const double r0 = M->rho0, U = M->U, P0 = M->P0;
+  J[0].v = r0;
+  ora_jet_term(&J[0], M, 0.05 * r0, 0, 0.0, 0.0, 1, x, t);
+  ora_jet_term(&J[0], M, 0.03 * r0, 1, 0.0, 0.0, 0, x, t);
+  ora_jet_term(&J[0], M, 0.02 * r0, 2, 0.0, 1.0, 0, x, t);
+  J[1].v = U * M->a;
+  ora_jet_term(&J[1], M, 0.035 * U, 0, 0.4, 0.0, 0, x, t);
+  ora_jet_term(&J[1], M, 0.025 * U, 1, 0.0, 0.0, 1, x, t);
+  J[2].v = U * M->a;
+  ora_jet_term(&J[2], M, 0.035 * U, 1, 0.9, 0.0, 1, x, t);
+  ora_jet_term(&J[2], M, 0.025 * U, 2, 0.0, 0.0, 0, x, t);
+  J[3].v = U * M->a;
+  ora_jet_term(&J[3], M, 0.025 * U, 2, 1.7, 0.0, 0, x, t);
+  ora_jet_term(&J[3], M, 0.015 * U, 0, 0.0, 1.0, 1, x, t);
+  J[4].v = P0;
+  ora_jet_term(&J[4], M, 0.05 * P0, 0, 1.2, 0.0, 0, x, t);
+  ora_jet_term(&J[4], M, 0.03 * P0, 1, 0.0, 1.0, 1, x, t);
+  ora_jet_term(&J[4], M, 0.02 * P0, 2, 0.6, 0.0, 1, x, t);
+}
+
+/* The source S = dQ/dt + div Phi of eq. 1 that makes the manufactured field an exact
+ * solution of eq. 2 (constant mu and kappa, T = p/rho), written out by hand with
+ * the product and chain rules from the primitive jets. */
+static void ora_mms_source_point(const ora_mms* M, const double x[3], double t, double S[5]) {
+  ora_jet J[5];
+  ora_mms_primitives(M, x, t, J);
+  const double g1 = M->gamma - 1.0;
+  const double rho = J[0].v, p = J[4].v;
+  const double* drho = J[0].g;
+  const double* dp = J[4].g;
+  double u[3], du[3][3], ut[3];  /* du[j][c] = d u_j / d x_c */
+  for (int j = 0; j < 3; ++j) {
+    u[j] = J[1 + j].v;
+    ut[j] = J[1 + j].t;
+    for (int c = 0; c < 3; ++c) du[j][c] = J[1 + j].g[c];
+  }
+  const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double E = p / g1 + 0.5 * rho * u2;
+  double theta = du[0][0] + du[1][1] + du[2][2];
+  /* d(theta)/dx_j = sum_c d^2 u_c / dx_j dx_c, and the Laplacian of u_j */
+  double dtheta[3], lap_u[3];
+  for (int j = 0; j < 3; ++j) {
+    dtheta[j] = 0.0;
+    lap_u[j] = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      dtheta[j] += J[1 + c].h[j][c];
+      lap_u[j] += J[1 + j].h[c][c];
+    }
+  }
+  /* Newtonian stress and its divergence (constant mu) */
+  double tau[3][3], div_tau[3];
+  for (int j = 0; j < 3; ++j) {
+    for (int c = 0; c < 3; ++c) tau[j][c] = M->mu * (du[j][c] + du[c][j] - (j == c ? 2.0 / 3.0 * theta : 0.0));
+    div_tau[j] = M->mu * (lap_u[j] + dtheta[j] / 3.0);
+  }
+  /* time derivatives of the conserved fields */
+  const double rho_t = J[0].t, p_t = J[4].t;
+  double udut = 0.0;
+  for (int j = 0; j < 3; ++j) udut += u[j] * ut[j];
+  const double E_t = p_t / g1 + 0.5 * rho_t * u2 + rho * udut;
+  /* gradient of E */
+  double dE[3];
+  for (int c = 0; c < 3; ++c) {
+    double udu = 0.0;
+    for (int j = 0; j < 3; ++j) udu += u[j] * du[j][c];
+    dE[c] = dp[c] / g1 + 0.5 * drho[c] * u2 + rho * udu;
+  }
+  /* mass */
+  double div_m = 0.0;
+  for (int c = 0; c < 3; ++c) div_m += drho[c] * u[c] + rho * du[c][c];
+  S[0] = rho_t + div_m;
+  /* momentum: d_t(rho u_j) + d_c(rho u_j u_c) + d_j p - d_c tau_jc */
+  for (int j = 0; j < 3; ++j) {
+    double adv = 0.0;
+    for (int c = 0; c < 3; ++c) adv += drho[c] * u[j] * u[c] + rho * du[j][c] * u[c] + rho * u[j] * du[c][c];
+    S[1 + j] = rho_t * u[j] + rho * ut[j] + adv + dp[j] - div_tau[j];
+  }
+  /* energy: d_t E + d_c((E + p) u_c) - d_c(tau_cj u_j) + d_c q_c, q = -kappa grad(p/rho) */
+  double adv = 0.0, work = 0.0;
+  for (int c = 0; c < 3; ++c) adv += (dE[c] + dp[c]) * u[c] + (E + p) * du[c][c];
+  for (int j = 0; j < 3; ++j) {
+    work += div_tau[j] * u[j];
+    for (int c = 0; c < 3; ++c) work += tau[c][j] * du[j][c];
+  }
+  double lap_T = 0.0;
+  for (int c = 0; c < 3; ++c)
+    lap_T += J[4].h[c][c] / rho - 2.0 * dp[c] * drho[c] / (rho * rho) - p * J[0].h[c][c] / (rho * rho) +
+             2.0 * p * drho[c] * drho[c] / (rho * rho * rho);
+  S[4] = E_t + adv - work - M->kappa * lap_T;
+}
+
+/* S[5][N] at every cell of P's lattice at lattice time t. */
+void ora_mms_source(const ora_params* P, const ora_mms* M, double t, double* S) {
+  const int64_t N = ora_cells(P);
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int z = 0; z < P->nz; ++z)
+    for (int y = 0; y < P->ny; ++y)
+      for (int x = 0; x < P->nx; ++x) {
+        const int64_t n = x + (int64_t)P->nx * (y + (int64_t)P->ny * z);
+        const double xx[3] = {(double)x, (double)y, (double)z};
+        double s[5];
+        ora_mms_source_point(M, xx, t, s);
+        for (int k = 0; k < 5; ++k) S[k * N + n] = s[k];
+      }
+}
+
+/* n steps with the manufactured source, the source of step t0 + s evaluated at
+ * lattice time t0 + s + t_frac (in place on return, work as in ora_run; S is scratch
+ * of 5N doubles). */
+void ora_run_mms(const ora_params* P, const ora_mms* M, double* f, double* work, double* S, int64_t nsteps,
+                 double t0, double t_frac) {
+  const int64_t N = ora_cells(P);
+  double* a = f;
+  double* b = work;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    ora_mms_source(P, M, t0 + (double)s + t_frac, S);
+    ora_step_src(P, a, b, NULL, S);
+    double* tmp = a;
+    a = b;
+    b = tmp;
+  }
+  if (a != f) memcpy(f, a, sizeof(double) * 35 * N);
+}
+
+int32_t ora_mms_size(void) { return (int32_t)sizeof(ora_mms); }

@@ -77,6 +77,76 @@ def conserved(rho, u, p, gamma):
     return Q
 
 
+# ---------------------------------------------------------- manufactured solution
+MMS_CFL = 0.05          # dt/dx, the acoustic time-step factor of the MMS row of Table 1
+MMS_OMEGA_FINEST = 1.86  # omega at the finest grid (n = 256) of the dt-tied relaxation
+MMS_N_FINEST = 256
+MMS_BETA_MAX = 4.0       # largest beta = 2 nu omega / c_s^2 on the finest grid (Sec. 2.4)
+
+
+def mms_fields(n, t, rho0=1.0, cs=0.5, mach=2.0, gamma=1.4, r=MMS_CFL):
+    """Primitive fields of eq. 8 in lattice units on the n^3 lattice (x = i / n, one
+    period per n cells) at lattice time t (steps; physical time t r / n).  Returns
+    (rho, (u_x, u_y, u_z), p) arrays [nz][ny][nx]."""
+    a = 0.30 / math.sqrt(3.0)
+    p0 = rho0 * cs * cs * (0.30 / mach) ** 2 / gamma
+    k = 2.0 * math.pi / n          # per cell
+    w = 2.0 * math.pi * r / n      # per step (unit period)
+    i = np.arange(n, dtype=np.float64)
+    Z, Y, X = np.meshgrid(i, i, i, indexing="ij")
+    U = r * cs                     # lattice velocity scale
+    P0 = r * r * p0                # lattice pressure scale
+    rho = rho0 * (1.0 + 0.05 * np.sin(k * X) + 0.03 * np.cos(k * Y) + 0.02 * np.cos(k * Z + w * t))
+    ux = U * (a + 0.035 * np.cos(k * X + 0.4) + 0.025 * np.sin(k * Y))
+    uy = U * (a + 0.035 * np.sin(k * Y + 0.9) + 0.025 * np.cos(k * Z))
+    uz = U * (a + 0.025 * np.cos(k * Z + 1.7) + 0.015 * np.sin(k * X + w * t))
+    p = P0 * (1.0 + 0.05 * np.cos(k * X + 1.2) + 0.03 * np.sin(k * Y + w * t) + 0.02 * np.sin(k * Z + 0.6))
+    return rho, (ux, uy, uz), p
+
+
+def mms(n=64, rho0=1.0, cs=0.5, mach=2.0, gamma=1.4, Pr=0.71, r=MMS_CFL, t_end=1.0,
+        omega_finest=MMS_OMEGA_FINEST, n_finest=MMS_N_FINEST, beta_max=MMS_BETA_MAX,
+        mu_phys=None) -> Case:
+    """Manufactured solution of Sec. 3.1 (eq. 8) on the unit periodic cube at n^3,
+    BGK, refined acoustically (dt/dx = r fixed) to physical time t_end.
+
+    Readings (the paper leaves them open): the fields of eq. 8 are physical with
+    c_s = 1/2 and dx = 1/n; the relaxation is tied to the time step as
+    1/omega - 1/2 proportional to dt, equal to omega_finest at n_finest; the physical
+    viscosity and conductivity are constant, with mu chosen so that beta reaches
+    beta_max on the finest grid (at the lowest density, 0.9 rho0) and kappa from Pr.
+    meta["mms"] holds the lattice constants the source needs: rho0, U, P0, a, K, W,
+    gamma, mu, kappa.  The viscosity follows from the paper-level reading (beta_max at
+    omega 1.86 on 256^3) unless mu_phys is given, whatever omega_finest/n_finest."""
+    a = 0.30 / math.sqrt(3.0)
+    p0 = rho0 * cs * cs * (0.30 / mach) ** 2 / gamma
+    steps = int(round(t_end * n / r))
+    nu_om = (1.0 / omega_finest - 0.5) * n_finest / n
+    omega = 1.0 / (0.5 + nu_om)
+    # beta = 8 nu_lat omega; nu_lat = mu_phys r n / rho on the lattice
+    if mu_phys is None:
+        mu_phys = (beta_max * 0.9 * rho0 /
+                   (8.0 * MMS_OMEGA_FINEST * r * MMS_N_FINEST))
+    mu_lat = mu_phys * r * n
+    rho, u, p = mms_fields(n, 0.0, rho0, cs, mach, gamma, r)
+    Q = conserved(rho, u, p, gamma)
+    U, P0 = r * cs, r * r * p0
+    prm = base_params(n, n, n, (PERIODIC, PERIODIC, PERIODIC), gamma=gamma, mu=mu_lat, Pr=Pr,
+                      mu_law=MU_CONSTANT, omega=omega, collision=BGK, p_min=1e-4 * r * r,
+                      rho_ref=rho0, E_ref=P0 / (gamma - 1.0) + 1.5 * rho0 * (U * a) ** 2)
+    meta = dict(r=r, steps=steps, t_end=t_end, mu_phys=mu_phys, omega=omega,
+                mms=dict(rho0=rho0, U=U, P0=P0, a=a, K=2.0 * math.pi / n, W=2.0 * math.pi * r / n,
+                         gamma=gamma, mu=mu_lat, kappa=prm["kappa_ref"]),
+                field_args=dict(rho0=rho0, cs=cs, mach=mach, gamma=gamma, r=r))
+    return Case("mms", prm, Q, steps, 0, meta)
+
+
+def mms_exact(case: Case, t) -> np.ndarray:
+    """Conserved fields of the manufactured solution at lattice time t."""
+    rho, u, p = mms_fields(case.params["nx"], t, **case.meta["field_args"])
+    return conserved(rho, u, p, case.meta["field_args"]["gamma"])
+
+
 # --------------------------------------------------------------------------- Sod
 def sod(n=256, ny=4, nz=4, r=0.128, t_end=0.2, left=(1.0, 1.0), right=(0.125, 0.1),
         gamma=1.4, Pr=0.71, mu=1e-6, omega=1.40, sensor_gain=20.0, J_min=3e-3,
