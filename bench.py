@@ -126,52 +126,81 @@ def bench_batch(count=64, steps=5000, seed=0, stream=None):
     return out
 
 
-def bench_precision(stream, n=128, steps=4000, diag_every=50, oracle_steps=200):
+def bench_precision(stream, n=128, steps=4000, diag_every=50):
     """FP16 shifted storage against FP32 storage (both FP32 arithmetic) on the
-    compressible Taylor-Green vortex at n^3, and both against the FP64 oracle over
-    its first oracle_steps steps: relative L2 over the diagnostic time series of
-    E_k, eps_s and eps_d, and of the conserved fields at the end of the oracle run."""
+    compressible Taylor-Green vortex at n^3: throughput of each, relative L2 over the
+    diagnostic time series of E_k, eps_s and eps_d, and of the conserved fields at
+    the end.  (Both against the FP64 oracle: tests/test_gpu_fp16.py.)"""
     import numpy as np
     import torch
-    import oracle
     from paper_2609_16361_amd import binding, inputs
     case = inputs.tgv(n=n, steps=steps, diag_every=diag_every)
     series, fields, rates = {}, {}, {}
     for name, stg in (("f32", binding.LBM_STORE_F32), ("f16", binding.LBM_STORE_F16)):
         with binding.Solver(case.params, storage=stg, stream=stream.cuda_stream) as s:
             s.init(case.Q0)
-            s.step(oracle_steps, diag_every)
-            fields[name] = s.moments()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            s.step(steps - oracle_steps, diag_every)
+            s.step(steps, diag_every)
             e1.record(stream)
             torch.cuda.synchronize()
-            rates[name] = case.cells * (steps - oracle_steps) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+            rates[name] = case.cells * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9
             recs, st = s.diagnostics()
             assert st == binding.LBM_OK
             series[name] = np.array([[r["Ek"], r["eps_s"], r["eps_d"]] for r in recs]) / case.cells
-    f, dor = oracle.run(case.params, oracle.init(case.params, case.Q0), oracle_steps, diag_every)
-    Qo = oracle.moments(case.params, f)
-    so = dor[:, :3] / case.cells
+            fields[name] = s.moments()
 
     def rel(a, b):
         return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
     k0 = 1  # the first record is the equilibrium start, where the gradients are zero
-    out = {"workload": f"compressible Taylor-Green {n}^3, {steps} steps, diagnostics every {diag_every}",
-           "glups": rates,
-           "f16_vs_f32_series": {q: rel(series["f16"][k0:, i], series["f32"][k0:, i])
-                                 for i, q in enumerate(("Ek", "eps_s", "eps_d"))},
-           "vs_oracle_series": {name: {q: rel(series[name][k0:len(so), i], so[k0:, i])
-                                       for i, q in enumerate(("Ek", "eps_s", "eps_d"))}
-                                for name in ("f32", "f16")},
-           "vs_oracle_fields": {name: [rel(fields[name][k], Qo[k]) for k in range(5)]
-                                for name in ("f32", "f16")},
-           "oracle_steps": oracle_steps,
-           "Ek_final": {name: float(series[name][-1, 0] * case.meta["ek_scale"]) for name in series},
-           "tc_final": steps * case.meta["tc_per_step"]}
+    return {"workload": f"compressible Taylor-Green {n}^3, {steps} steps, diagnostics every {diag_every}",
+            "glups": rates,
+            "f16_vs_f32_series": {q: rel(series["f16"][k0:, i], series["f32"][k0:, i])
+                                  for i, q in enumerate(("Ek", "eps_s", "eps_d"))},
+            "f16_vs_f32_fields": [rel(fields["f16"][k], fields["f32"][k]) for k in range(5)],
+            "Ek_final": {name: float(series[name][-1, 0] * case.meta["ek_scale"]) for name in series},
+            "tc_final": steps * case.meta["tc_per_step"]}
+
+
+def bench_mms(stream, sizes=(64, 128, 256), frac=0.5):
+    """Order of accuracy on the manufactured solution of Sec. 3.1 (eq. 8), FP32 on the
+    GPU: relative L2 error of each conserved field at t = 1 against the exact field
+    at n^3 for each n, the empirical order of convergence from each pair, and the
+    throughput.  The source is evaluated on the GPU each step at the step's mid-time."""
+    import numpy as np
+    import torch
+    from paper_2609_16361_amd import binding, inputs
+    out = {"sizes": list(sizes), "errors": {}, "eoc": {}, "glups": {}, "omega": {}, "steps": {}}
+    prev = None
+    for n in sizes:
+        case = inputs.mms(n)
+        S = torch.empty(5 * n ** 3, dtype=torch.float32, device="cuda")
+        with binding.Solver(case.params, stream=stream.cuda_stream) as s:
+            s.init(case.Q0)
+            s.set_source(S.data_ptr())
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for step in range(case.steps):
+                binding.lbm_mms_source(case.meta["mms"], n, n, n, step + frac, S.data_ptr(), stream.cuda_stream)
+                s.step(1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            Q = s.moments()
+        del S
+        Qe = inputs.mms_exact(case, case.steps)
+        err = [float(np.linalg.norm(Q[k] - Qe[k]) / np.linalg.norm(Qe[k])) for k in range(5)]
+        out["errors"][n] = err
+        out["omega"][n] = case.meta["omega"]
+        out["steps"][n] = case.steps
+        out["glups"][n] = case.cells * case.steps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        if prev is not None:
+            out["eoc"][f"{prev[0]}->{n}"] = [float(np.log2(a / b)) for a, b in zip(prev[1], err)]
+        prev = (n, err)
+        print(f"mms {n}^3: errors {['%.3e' % e for e in err]}", file=sys.stderr, flush=True)
     return out
 
 
@@ -254,6 +283,8 @@ def main():
                     help="only the FP16-storage precision study (128^3 vortex)")
     ap.add_argument("--fp16", action="store_true", help="FP16 population storage for the main workload")
     ap.add_argument("--serve-only", action="store_true", help="only the serving mix")
+    ap.add_argument("--mms-only", action="store_true",
+                    help="only the manufactured-solution convergence study (64^3-256^3)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving mix")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
@@ -282,6 +313,9 @@ def main():
         return
     if args.precision_only:
         print(json.dumps({"precision": bench_precision(stream)}), flush=True)
+        return
+    if args.mms_only:
+        print(json.dumps({"mms": bench_mms(stream)}), flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serve": bench_serve(stream, count=args.serve_requests)}), flush=True)

@@ -167,6 +167,17 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t nontemporal, int32_t blocks_per_cu,
                           int32_t odd_lds);
 
+/* Source term S of eq. 1 for the following steps: S_dev points to device memory
+ * S[5][nz][ny][nx] (FP32, lattice units per step, field order rho, rho u_x,
+ * rho u_y, rho u_z, E), projected onto the lattice weights and added to the
+ * post-collision populations of every step (Algorithm 1, last line:
+ * f*_ki += w_i S_k).  The caller owns the array, keeps it alive while steps that
+ * use it are in flight, and may rewrite it between steps in stream order (a
+ * time-dependent source is evaluated once per step).  NULL switches the source
+ * off (the default; no extra traffic).  FP32 storage only: EINVAL for FP16.  Steps
+ * with a source always use nontemporal access. */
+lbm_status lbm_set_source(lbm_ctx* ctx, const float* S_dev);
+
 /* Completed steps. */
 lbm_status lbm_get_step(lbm_ctx* ctx, int64_t* step);
 

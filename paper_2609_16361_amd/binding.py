@@ -77,6 +77,12 @@ _lib = None
 # name -> (restype, argtypes)
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
+class lbm_mms(ctypes.Structure):
+    """Constants of the manufactured solution (include/grlbm_mms.h), lattice units."""
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("rho0", "U", "P0", "a", "K", "W", "gamma", "mu", "kappa")]
+
+
 SIGNATURES = {
     "lbm_state_bytes": (ctypes.c_size_t, [_P(lbm_params)]),
     "lbm_create": (ctypes.c_int, [_P(lbm_params), _vp, _P(_vp)]),
@@ -90,6 +96,9 @@ SIGNATURES = {
     "lbm_get_populations": (ctypes.c_int, [_vp, _P(ctypes.c_float), _P(ctypes.c_int64)]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _P(ctypes.c_float), ctypes.c_int64]),
     "lbm_set_launch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_set_source": (ctypes.c_int, [_vp, _vp]),
+    "lbm_mms_source": (ctypes.c_int, [_P(lbm_mms), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_double, _vp, _vp]),
     "lbm_get_step": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "lbm_destroy": (ctypes.c_int, [_vp]),
     "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_double)]),
@@ -263,6 +272,19 @@ def lbm_bw_probe(nbytes: int, iters: int = 10) -> float:
     return g.value
 
 
+def lbm_set_source(ctx: int, S_dev: int | None) -> None:
+    """S_dev: device address of S[5][nz][ny][nx] FP32 (e.g. tensor.data_ptr()), or
+    None to switch the source off."""
+    _check(load().lbm_set_source(ctx, S_dev), "lbm_set_source")
+
+
+def lbm_mms_source(m: dict, nx: int, ny: int, nz: int, t: float, S_dev: int, stream: int | None = None) -> None:
+    """Manufactured-solution source at lattice time t into S_dev (FP32 [5][nz][ny][nx])."""
+    mm = lbm_mms(*[float(m[n]) for n, _ in lbm_mms._fields_])
+    _check(load().lbm_mms_source(ctypes.byref(mm), int(nx), int(ny), int(nz), float(t), S_dev, stream),
+           "lbm_mms_source")
+
+
 def lbm_last_error() -> str:
     return load().lbm_last_error().decode(errors="replace")
 
@@ -289,6 +311,9 @@ class Solver:
 
     def step(self, n, diag_every=0):
         lbm_step(self.ctx, n, diag_every)
+
+    def set_source(self, S_dev):
+        lbm_set_source(self.ctx, S_dev)
 
     def moments(self):
         return lbm_moments(self.ctx, self.shape)

@@ -14,7 +14,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgrlbm.so")
-SOURCES = ["grlbm_kernels.hip", "grlbm_api.hip", "grlbm_batch.hip"]
+SOURCES = ["grlbm_kernels.hip", "grlbm_api.hip", "grlbm_batch.hip", "grlbm_mms.hip"]
 ARCH = "gfx950"
 
 

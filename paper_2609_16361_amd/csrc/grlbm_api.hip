@@ -214,6 +214,7 @@ struct lbm_ctx {
   bool nt = true;
   int lds = 0;
   bool odd_lds = true;
+  const float* src = nullptr;  // caller-owned source of eq. 1, [5][N] FP32, or nullptr
   float* partials = nullptr;
   int64_t partials_blocks = 0;
   float* ring = nullptr;
@@ -348,6 +349,15 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t nontemporal, int32_
   return LBM_OK;
 }
 
+lbm_status lbm_set_source(lbm_ctx* c, const float* S_dev) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (S_dev && c->p.storage != LBM_STORE_F32)
+    return fail(LBM_EINVAL, "a source term needs FP32 population storage");
+  if (S_dev && ((uintptr_t)S_dev) % sizeof(float) != 0) return fail(LBM_EINVAL, "source is not 4-byte aligned");
+  c->src = S_dev;
+  return LBM_OK;
+}
+
 lbm_status lbm_init_fields_device(lbm_ctx* c, const double* Q_dev) {
   if (!c || !Q_dev) return fail(LBM_EINVAL, "ctx or Q is NULL");
   if (c->p.storage == LBM_STORE_F16) {
@@ -393,6 +403,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n, int32_t diag_every) {
   L.nt = c->nt;
   L.lds = c->lds;
   L.odd_lds = c->odd_lds;
+  L.src = c->src;
   L.partials = nullptr;
   if (diag_every > 0) {
     lbm_status st = ensure_partials(c);

@@ -333,13 +333,28 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
   }
 }
 
+// ---------------------------------------------------------------- source term
+// The source S of eq. 1 projected onto the lattice weights and added to the
+// post-collision populations (Algorithm 1, last line): f*_ki += w_i S_k.  src holds
+// the step's source per cell, src[5][N] with N the cell count, lattice units.
+__device__ __forceinline__ void add_source(float f[kPop], const float* __restrict__ src, int64_t N,
+                                           int64_t n) {
+#pragma unroll
+  for (int k = 0; k < kFields; ++k) {
+    const float s = src[k * N + n];
+    f[7 * k] += 0.25f * s;
+#pragma unroll
+    for (int i = 1; i < kQ; ++i) f[7 * k + i] += 0.125f * s;
+  }
+}
+
 // ----------------------------------------------------------------- one cell
 // One cell's AA half step: gather the post-stream populations, run the collision of
 // Algorithm 1 in registers, scatter the post-collision ones.  F points at slot 0 of
 // the instance's arrays.  With DIAG, vals[9] receives the cell's diagnostic densities.
-template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT>
+template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC = false>
 __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, const Coll& c, int x,
-                                            int y, int z, float* vals) {
+                                            int y, int z, float* vals, const float* __restrict__ src = nullptr) {
   const Nbr b = make_nbr(g, x, y, z);
   const int64_t S = g.S;
   float f[kPop];
@@ -366,6 +381,7 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
     for (int k = 0; k < 5; ++k) vals[3 + k] = d.dq[k];
     vals[8] = d.nonfinite;
   }
+  if constexpr (SRC) add_source(f, src, (int64_t)g.nx * g.ny * g.nz, b.n);
   // store half of AA
 #pragma unroll
   for (int k = 0; k < kFields; ++k) {
@@ -428,9 +444,10 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
 // false asserts that the tile holds whole x-rows (then every x location is in the
 // tile and the edge handling compiles away).  The collision is the same call as in
 // cell_update, so the results are bitwise those of cell_update<true, ...>.
-template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool EDGES = true>
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool EDGES = true, bool SRC = false>
 __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g, const Coll& c, int n0,
-                                                bool act, int x, int y, int z, float* xs, float* vals) {
+                                                bool act, int x, int y, int z, float* xs, float* vals,
+                                                const float* __restrict__ src = nullptr) {
   const int B = blockDim.x;
   const int lane = threadIdx.x;
   const Nbr b = make_nbr(g, x, y, z);
@@ -495,6 +512,7 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
       for (int k = 0; k < 5; ++k) vals[3 + k] = d.dq[k];
       vals[8] = d.nonfinite;
     }
+    if constexpr (SRC) add_source(f, src, (int64_t)g.nx * g.ny * g.nz, b.n);
 #pragma unroll
     for (int k = 0; k < kFields; ++k) {
       T* Fk = F + (int64_t)(7 * k) * S;

@@ -3,7 +3,7 @@
 //   k_step      fused collide-and-stream update of one AA half step (even or odd
 //               parity): 35 loads, the collision of Algorithm 1 in registers, 35
 //               stores; optional fused diagnostics (wavefront shuffle + LDS
-//               reduction to one partial per block)
+//               reduction to one partial per block) and an optional source term
 //   k_step_odd_tiles  the odd half step over linear tiles of cells with the +-x
 //               populations shifted in LDS, so every HBM access stays aligned
 //   k_finalize  deterministic reduction of the per-block partials into one record
@@ -70,16 +70,16 @@ __device__ void block_reduce_store(float vals[kDiagVals], float* __restrict__ ou
 }
 
 // ------------------------------------------------------------------ the update
-template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT>
-__global__ void __launch_bounds__(1024) k_step(T* __restrict__ F, Grid g, Coll c,
-                                                float* __restrict__ partials) {
+template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC = false>
+__global__ void __launch_bounds__(1024) k_step(T* __restrict__ F, Grid g, Coll c, float* __restrict__ partials,
+                                                const float* __restrict__ src) {
   const CellPos pos = block_cell(g);
   float vals[kDiagVals];
   if constexpr (DIAG) {
 #pragma unroll
     for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
   }
-  if (pos.active) cell_update<ODD, COLL, T, ZG, DIAG, NT>(F, g, c, pos.x, pos.y, pos.z, vals);
+  if (pos.active) cell_update<ODD, COLL, T, ZG, DIAG, NT, SRC>(F, g, c, pos.x, pos.y, pos.z, vals, src);
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
@@ -88,9 +88,10 @@ __global__ void __launch_bounds__(1024) k_step(T* __restrict__ F, Grid g, Coll c
 // block per x-row (nx <= 1024, blockDim.x = nx rounded up to 64); otherwise linear
 // tiles of blockDim.x cells that may start mid-row.  Bitwise the same result as
 // k_step's odd step.
-template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool ROWS>
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool ROWS, bool SRC = false>
 __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid g, Coll c,
-                                                          float* __restrict__ partials) {
+                                                          float* __restrict__ partials,
+                                                          const float* __restrict__ src) {
   extern __shared__ float xs[];
   int n0, x = 0, y = 0, z = 0;
   bool act;
@@ -117,7 +118,7 @@ __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid
 #pragma unroll
     for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
   }
-  tile_update_odd<COLL, T, ZG, DIAG, NT, !ROWS>(F, g, c, n0, act, x, y, z, xs, vals);
+  tile_update_odd<COLL, T, ZG, DIAG, NT, !ROWS, SRC>(F, g, c, n0, act, x, y, z, xs, vals, src);
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
@@ -272,57 +273,60 @@ __global__ void __launch_bounds__(256) k_copy(const v4f* __restrict__ a, v4f* __
 // `lds` bytes of dynamic LDS are reserved per block (and never touched): with 160 KB
 // of LDS per CU this caps the resident blocks per CU, which the 35-stream access
 // pattern prefers low (about 16 waves per CU).
-template <bool ODD, int COLL, typename T, bool ZG, bool DIAG>
-static hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
+template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC>
+static hipError_t launch_step_nt(const StepLaunch& L, hipStream_t s) {
   const Grid& g = L.g;
   T* F = (T*)L.F;
   if (ODD && L.odd_lds) {
     const OddTiles ot = odd_tiles(g);
-    if (ot.rows) {
-      if (L.nt)
-        hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, true, true>), dim3((unsigned)ot.blocks),
-                           dim3(ot.block), ot.lds, s, F, g, L.c, L.partials);
-      else
-        hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, false, true>), dim3((unsigned)ot.blocks),
-                           dim3(ot.block), ot.lds, s, F, g, L.c, L.partials);
-    } else {
-      if (L.nt)
-        hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, true, false>), dim3((unsigned)ot.blocks),
-                           dim3(ot.block), ot.lds, s, F, g, L.c, L.partials);
-      else
-        hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, false, false>), dim3((unsigned)ot.blocks),
-                           dim3(ot.block), ot.lds, s, F, g, L.c, L.partials);
-    }
+    if (ot.rows)
+      hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, true, SRC>), dim3((unsigned)ot.blocks),
+                         dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src);
+    else
+      hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, false, SRC>), dim3((unsigned)ot.blocks),
+                         dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src);
     return hipGetLastError();
   }
   const int64_t blocks = step_blocks(g, L.block);
-  if (L.nt)
-    hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, true>), dim3((unsigned)blocks), dim3(L.block), L.lds,
-                       s, F, g, L.c, L.partials);
-  else
-    hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, false>), dim3((unsigned)blocks), dim3(L.block),
-                       L.lds, s, F, g, L.c, L.partials);
+  hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, NT, SRC>), dim3((unsigned)blocks), dim3(L.block), L.lds, s,
+                     F, g, L.c, L.partials, L.src);
   return hipGetLastError();
 }
 
-template <typename T, bool ZG, bool DIAG>
+// With a source only FP32 storage and nontemporal access are instantiated (the
+// access mode never changes results; lbm_set_source rejects FP16 storage).
+template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool SRC>
+static hipError_t launch_step_t(const StepLaunch& L, hipStream_t s) {
+  if constexpr (SRC) {
+    return launch_step_nt<ODD, COLL, T, ZG, DIAG, true, true>(L, s);
+  } else {
+    return L.nt ? launch_step_nt<ODD, COLL, T, ZG, DIAG, true, false>(L, s)
+                : launch_step_nt<ODD, COLL, T, ZG, DIAG, false, false>(L, s);
+  }
+}
+
+template <typename T, bool ZG, bool DIAG, bool SRC>
 static hipError_t dispatch_odd_coll(const StepLaunch& L, hipStream_t s) {
   const bool odd = L.odd;
   if (L.coll == 0)
-    return odd ? launch_step_t<true, 0, T, ZG, DIAG>(L, s) : launch_step_t<false, 0, T, ZG, DIAG>(L, s);
-  return odd ? launch_step_t<true, 1, T, ZG, DIAG>(L, s) : launch_step_t<false, 1, T, ZG, DIAG>(L, s);
+    return odd ? launch_step_t<true, 0, T, ZG, DIAG, SRC>(L, s) : launch_step_t<false, 0, T, ZG, DIAG, SRC>(L, s);
+  return odd ? launch_step_t<true, 1, T, ZG, DIAG, SRC>(L, s) : launch_step_t<false, 1, T, ZG, DIAG, SRC>(L, s);
 }
 
-template <typename T>
+template <typename T, bool SRC>
 static hipError_t dispatch_t(const StepLaunch& L, hipStream_t s) {
   const bool zg = L.g.zg_x || L.g.zg_y || L.g.zg_z;
-  if (zg) return L.diag ? dispatch_odd_coll<T, true, true>(L, s) : dispatch_odd_coll<T, true, false>(L, s);
-  return L.diag ? dispatch_odd_coll<T, false, true>(L, s) : dispatch_odd_coll<T, false, false>(L, s);
+  if (zg)
+    return L.diag ? dispatch_odd_coll<T, true, true, SRC>(L, s) : dispatch_odd_coll<T, true, false, SRC>(L, s);
+  return L.diag ? dispatch_odd_coll<T, false, true, SRC>(L, s) : dispatch_odd_coll<T, false, false, SRC>(L, s);
 }
 
 hipError_t launch_step(const StepLaunch& L, hipStream_t s) {
-  if (L.f16) return dispatch_t<_Float16>(L, s);
-  return dispatch_t<float>(L, s);
+  if (L.f16) {
+    if (L.src) return hipErrorInvalidValue;  // rejected earlier by lbm_set_source
+    return dispatch_t<_Float16, false>(L, s);
+  }
+  return L.src ? dispatch_t<float, true>(L, s) : dispatch_t<float, false>(L, s);
 }
 
 int64_t step_blocks(const Grid& g, int block) {

@@ -1,6 +1,6 @@
 """Host-side checks of the C ABI (no GPU needed).
 
-* the HIP library loads and exports every function include/grlbm.h declares
+* the HIP library loads and exports every function the headers in include/ declare
 * the ctypes mirrors of lbm_params / lbm_diag match the C layout (checked with a
   small C program compiled by gcc against the header)
 * lbm_state_bytes: 35 padded arrays; 140 B/cell FP32 and 70 B/cell FP16 (Sec. 4:
@@ -18,12 +18,16 @@ from paper_2609_16361_amd import binding, inputs
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "grlbm.h")
+HEADERS = sorted(os.path.join(ROOT, "include", h) for h in os.listdir(os.path.join(ROOT, "include"))
+                 if h.endswith(".h"))
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(lbm_\w+)\s*\(", src, flags=re.M)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(lbm_\w+)\s*\(", src, flags=re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -49,6 +53,43 @@ def test_struct_layout_matches_header(tmp_path):
     P, D = binding.lbm_params, binding.lbm_diag
     assert vals == [ctypes.sizeof(P), P.gamma.offset, P.omega.offset, P.E_ref.offset,
                     ctypes.sizeof(D), D.nonfinite.offset]
+
+
+def test_mms_struct_layout_matches_header(tmp_path):
+    prog = tmp_path / "mms.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "grlbm_mms.h"\n'
+                    'int main(void){printf("%zu %zu\\n", sizeof(lbm_mms), offsetof(lbm_mms, kappa));'
+                    ' return 0;}\n')
+    exe = tmp_path / "mms"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
+    vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()))
+    M = binding.lbm_mms
+    assert vals == [ctypes.sizeof(M), M.kappa.offset]
+
+
+def test_generated_mms_kernel_is_current():
+    """csrc/grlbm_mms.hip is what the generator produces from eq. 2 and eq. 8."""
+    from paper_2609_16361_amd import mms_codegen
+    assert open(mms_codegen.OUT).read() == mms_codegen.generate()
+
+
+def test_generator_source_matches_oracle():
+    """The SymPy source behind the generated kernel and the oracle's hand-written
+    source are two derivations of the same residual of eq. 2."""
+    import numpy as np
+    import sympy as sp
+    import oracle
+    from paper_2609_16361_amd import mms_codegen
+    (x, y, z, t), c, S = mms_codegen.source_expressions()
+    case = inputs.mms(n=10)
+    m = case.meta["mms"]
+    sub = {c[k]: m[k] for k in mms_codegen.CONSTS}
+    f = sp.lambdify((x, y, z, t), [e.subs(sub) for e in S], "math")
+    So = oracle.mms_source(case.params, m, 3.5)
+    for i, j, l in ((0, 0, 0), (3, 7, 1), (9, 2, 5)):
+        ref = f(float(i), float(j), float(l), 3.5)
+        for k in range(5):
+            assert abs(So[k, l, j, i] - ref[k]) <= 1e-11 * max(abs(ref[k]), 1e-3 * np.abs(So[k]).max())
 
 
 def test_state_bytes():

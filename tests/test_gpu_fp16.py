@@ -90,3 +90,34 @@ def test_fp16_checkpoint_roundtrip():
         s2.step(4)
         f2, _ = s2.populations()
     assert np.array_equal(f1, f2)
+
+
+def test_precision_workload_against_oracle():
+    """The FP16 precision workload (cTGV 128^3, f_mu 0.9) over its first 100 steps:
+    the E_k / eps_s / eps_d series (every 10 steps) and the conserved fields of FP32
+    and FP16 storage against the FP64 oracle.  Bars: FP32 at its smooth-data level;
+    FP16 a few times the relative FP16 step 2^-11 (and ~10x the measured values)."""
+    case = inputs.tgv(n=128, steps=100, diag_every=10)
+    out = {}
+    for name, stg in (("f32", binding.LBM_STORE_F32), ("f16", F16)):
+        say(f"precision workload 128^3 {name}")
+        with binding.Solver(case.params, storage=stg) as s:
+            s.init(case.Q0)
+            s.step(100, 10)
+            recs, st = s.diagnostics()
+            assert st == binding.LBM_OK
+            out[name] = (np.array([[r["Ek"], r["eps_s"], r["eps_d"]] for r in recs]), s.moments())
+    say("precision workload 128^3 oracle")
+    f, d = oracle.run(case.params, oracle.init(case.params, case.Q0), 100, 10)
+    Qo = oracle.moments(case.params, f)
+    so = d[:, :3]
+    bars = {"f32": ((1e-6, 1e-4, 1e-4), 2e-5), "f16": ((1e-3, 3e-2, 2e-2), 1e-2)}
+    for name, (ser, Q) in out.items():
+        for i, q in enumerate(("Ek", "eps_s", "eps_d")):
+            e = np.linalg.norm(ser[1:, i] - so[1:, i]) / np.linalg.norm(so[1:, i])
+            say(f"   {name} {q} series vs oracle {e:.2e}")
+            assert e <= bars[name][0][i], (name, q, e)
+        for k in range(5):
+            e = np.linalg.norm(Q[k] - Qo[k]) / np.linalg.norm(Qo[k])
+            say(f"   {name} field {k} vs oracle {e:.2e}")
+            assert e <= bars[name][1], (name, k, e)
