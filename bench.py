@@ -204,6 +204,36 @@ def bench_mms(stream, sizes=(64, 128, 256), frac=0.5):
     return out
 
 
+def bench_spectral(stream, n=128, tc_samples=(1.0, 2.0, 3.0, 4.0, 5.0)):
+    """The dissipation channels of the compressible Taylor-Green vortex at n^3: the
+    fused in-collision values (reconstructed gradients) against the spectral values
+    of the same state (Fourier derivatives of lbm_moments output, Sec. 3.3), at
+    several convective times, in the paper's units (divided by rho0, converted)."""
+    from paper_2609_16361_amd import binding, inputs, spectral
+    case = inputs.tgv(n=n, diag_every=0)
+    scale = case.meta["eps_scale"]
+    rows = []
+    with binding.Solver(case.params, stream=stream.cuda_stream) as s:
+        s.init(case.Q0)
+        done = 0
+        for tc in tc_samples:
+            target = int(round(tc / case.meta["tc_per_step"]))
+            s.step(target - done)
+            Q = s.moments()
+            s.step(1, 1)                  # the fused record of this state
+            done = target + 1
+            recs, st = s.diagnostics()
+            assert st == binding.LBM_OK and recs[-1]["step"] == target
+            ek, es, ed = spectral.channels(Q, case.params)
+            fs, fd = recs[-1]["eps_s"] / case.cells, recs[-1]["eps_d"] / case.cells
+            rows.append({"tc": target * case.meta["tc_per_step"], "step": target,
+                         "eps_s": {"fused": fs * scale, "spectral": es * scale, "ratio": fs / es},
+                         "eps_d": {"fused": fd * scale, "spectral": ed * scale, "ratio": fd / ed}})
+            print(f"spectral t_c {rows[-1]['tc']:.2f}: eps_s ratio {fs / es:.3f} eps_d ratio {fd / ed:.3f}",
+                  file=sys.stderr, flush=True)
+    return {"workload": f"compressible Taylor-Green {n}^3", "samples": rows}
+
+
 def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9, chunk=50,
                 max_active_cells=8 * 2 ** 20):
     """Serving mix (Poisson arrivals at `rate`, 40% Sod variants, 40% Taylor-Green,
@@ -283,6 +313,8 @@ def main():
                     help="only the FP16-storage precision study (128^3 vortex)")
     ap.add_argument("--fp16", action="store_true", help="FP16 population storage for the main workload")
     ap.add_argument("--serve-only", action="store_true", help="only the serving mix")
+    ap.add_argument("--spectral-only", action="store_true",
+                    help="only the fused vs spectral dissipation comparison (cTGV 128^3)")
     ap.add_argument("--mms-only", action="store_true",
                     help="only the manufactured-solution convergence study (64^3-256^3)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving mix")
@@ -313,6 +345,9 @@ def main():
         return
     if args.precision_only:
         print(json.dumps({"precision": bench_precision(stream)}), flush=True)
+        return
+    if args.spectral_only:
+        print(json.dumps({"spectral": bench_spectral(stream)}), flush=True)
         return
     if args.mms_only:
         print(json.dumps({"mms": bench_mms(stream)}), flush=True)
