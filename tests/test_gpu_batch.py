@@ -143,3 +143,40 @@ def test_becker_mix_against_oracle():
             for k in (0, 1, 4):
                 e = np.linalg.norm(Q[k] - Qo[k]) / np.linalg.norm(Qo[k])
                 assert e <= 2e-5, (c.params["nx"], k, e)
+
+
+def test_full_becker_batch_sampled_against_oracle():
+    """The batched workload at its full size and in the launch configuration the
+    benchmark times: all 64 seeded tubes (4.5 M cells) in one batch, graphs of 50
+    steps, autotuned shape, 5000 steps.  Three instances (the shortest, and two near
+    the top of the Mach range) are checked against the FP64 oracle: uniform across
+    the tube, relative L2 <= 1e-3 in shocked cells (oracle sensor active at the end,
+    dilated by 4 cells) and over the tube for rho, rho u_x and E."""
+    cases = inputs.becker_batch(64, seed=0)
+    steps = 5000
+    nbytes = sum(binding.lbm_state_bytes(binding.make_params(c.params)) for c in cases)
+    sample = (23, 41, 6)
+    with binding.Batch(int(nbytes * 1.05) + (64 << 20), max_instances=64, graph_steps=50) as b:
+        ids = [b.add(c.params, c.Q0, steps) for c in cases]
+        say("autotune the full Becker batch")
+        b.autotune(trial_steps=50)
+        say("run 5000 steps")
+        b.run(steps)
+        Qs = {j: b.moments(ids[j]) for j in sample}
+    for j in sample:
+        c = cases[j]
+        nx = c.params["nx"]
+        Q = Qs[j]
+        say(f"becker instance {j}: L={nx} M={c.meta['mach']:.2f} vs oracle, {steps} steps")
+        assert np.array_equal(Q, np.broadcast_to(Q[:, :1, :1, :], Q.shape))
+        f, _ = oracle.run(c.params, oracle.init(c.params, c.Q0), steps)
+        Qo = oracle.moments(c.params, f)
+        fo = f.reshape(35, 4, 4, nx)[:, 0, 0, :]
+        chi = np.array([oracle.collide(c.params, fo[:, x])[1]["chi"] for x in range(nx)])
+        mask = np.convolve((chi > 0).astype(float), np.ones(9), mode="same") > 0
+        for k in (0, 1, 4):
+            e_all = np.linalg.norm(Q[k] - Qo[k]) / np.linalg.norm(Qo[k])
+            e_sh = (np.linalg.norm(Q[k][..., mask] - Qo[k][..., mask]) / np.linalg.norm(Qo[k][..., mask])
+                    if mask.any() else 0.0)
+            say(f"   field {k}: overall {e_all:.2e} shocked {e_sh:.2e} ({int(mask.sum())} cells)")
+            assert e_all <= 1e-3 and e_sh <= 1e-3, (j, k, e_all, e_sh)
