@@ -414,6 +414,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n, int32_t diag_every) {
     const bool diag = diag_every > 0 && (t % diag_every) == 0;
     L.odd = (t & 1) != 0;
     L.diag = diag;
+    L.skey = grlbm::step_key(t);
     if (diag) {
       if (c->ring_used == kRingCap) {
         lbm_status st = drain_ring(c);

@@ -88,17 +88,18 @@ __global__ void __launch_bounds__(1024) k_batch_step(T* __restrict__ arena, cons
     // results are bitwise the same
     const bool odd = ((t - ts) & 1) != 0;
     const bool zg = g.zg_x | g.zg_y | g.zg_z;
+    const uint32_t skey = step_key(t - ts);  // the instance's own step index
     if (odd) {
       // every lane takes part (barriers inside)
       if (zg)
-        tile_update_odd<COLL, T, true, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr);
+        tile_update_odd<COLL, T, true, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr, skey);
       else
-        tile_update_odd<COLL, T, false, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr);
+        tile_update_odd<COLL, T, false, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr, skey);
     } else if (act) {
       if (zg)
-        cell_update<false, COLL, T, true, false, NT>(F, g, c, x, y, z, nullptr);
+        cell_update<false, COLL, T, true, false, NT>(F, g, c, x, y, z, nullptr, skey);
       else
-        cell_update<false, COLL, T, false, false, NT>(F, g, c, x, y, z, nullptr);
+        cell_update<false, COLL, T, false, false, NT>(F, g, c, x, y, z, nullptr, skey);
     }
   }
 }

@@ -124,6 +124,48 @@ __device__ __forceinline__ void st(T* p, float v) {
   }
 }
 
+// ----------------------------------------------- FP16 stochastic rounding
+// Round-to-nearest storage of a quasi-steady population rounds it the same way at
+// every step, and the conserved fields drift by a fraction of an FP16 ulp per step.
+// FP16 populations are therefore rounded stochastically: the 13 FP32 mantissa bits
+// below FP16's 10 receive a uniform dither before they are cut off, so a value
+// rounds up with probability equal to its distance from the lower FP16 neighbour
+// and the rounding error has zero mean.  The dither of a stored element is a
+// counter-based hash of its destination cell, its slot and the step, so every path
+// that writes the element (even or odd step, direct or LDS-staged, single context
+// or batch) stores the same bits.
+
+// 32-bit integer finaliser (xor-shift and multiply rounds, "lowbias32").
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Key of one step (the index of the step being taken, counted per instance).
+__host__ __device__ __forceinline__ uint32_t step_key(int64_t step) {
+  return mix32((uint32_t)step * 0x9e3779b9u + 0x632be5abu);
+}
+
+// Hash of a destination cell under a step key.
+__device__ __forceinline__ uint32_t cell_key(int64_t cell, uint32_t skey) { return mix32((uint32_t)cell ^ skey); }
+
+// Stores population slot `slot` (7 k + i) of a cell whose key is hc.  FP32: plain
+// store.  FP16: stochastic rounding as above (the rounded value is exact in FP16,
+// so the conversion itself no longer rounds).
+template <typename T, bool NT>
+__device__ __forceinline__ void st_pop(T* p, float v, uint32_t hc, int slot) {
+  if constexpr (sizeof(T) == 2) {
+    const uint32_t mul = 0x9e3779b9u + 2u * (uint32_t)slot * 0x6c8e9cf5u;  // odd per slot
+    const uint32_t dither = (hc * mul) >> 19;                               // 13 bits
+    v = __uint_as_float((__float_as_uint(v) + dither) & 0xffffe000u);
+  }
+  st<T, NT>(p, v);
+}
+
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Per-cell diagnostic densities (Sec. 3.3 channels) of the pre-collision state.
@@ -354,7 +396,8 @@ __device__ __forceinline__ void add_source(float f[kPop], const float* __restric
 // the instance's arrays.  With DIAG, vals[9] receives the cell's diagnostic densities.
 template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC = false>
 __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, const Coll& c, int x,
-                                            int y, int z, float* vals, const float* __restrict__ src = nullptr) {
+                                            int y, int z, float* vals, uint32_t skey,
+                                            const float* __restrict__ src = nullptr) {
   const Nbr b = make_nbr(g, x, y, z);
   const int64_t S = g.S;
   float f[kPop];
@@ -382,38 +425,50 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
     vals[8] = d.nonfinite;
   }
   if constexpr (SRC) add_source(f, src, (int64_t)g.nx * g.ny * g.nz, b.n);
-  // store half of AA
+  // store half of AA; FP16 dither keys of the destination cells
+  const bool f16 = sizeof(T) == 2;
+  const uint32_t hn = f16 ? cell_key(b.n, skey) : 0u;
+  uint32_t hxp = 0u, hxm = 0u, hyp = 0u, hym = 0u, hzp = 0u, hzm = 0u;
+  if constexpr (ODD && sizeof(T) == 2) {
+    hxp = cell_key(b.xp, skey);
+    hxm = cell_key(b.xm, skey);
+    hyp = cell_key(b.yp, skey);
+    hym = cell_key(b.ym, skey);
+    hzp = cell_key(b.zp, skey);
+    hzm = cell_key(b.zm, skey);
+  }
 #pragma unroll
   for (int k = 0; k < kFields; ++k) {
     T* Fk = F + (int64_t)(7 * k) * S;
     const float* fo = f + 7 * k;
+    const int s0 = 7 * k;
     if constexpr (!ODD) {
       // own cell, opposite slot; on a zero-gradient face the ghost copy replaces
       // the population that leaves the domain
-      st<T, NT>(Fk + b.n, fo[0]);
-      st<T, NT>(Fk + 1 * S + b.n, (ZG && b.lo_x) ? fo[1] : fo[2]);
-      st<T, NT>(Fk + 2 * S + b.n, (ZG && b.hi_x) ? fo[2] : fo[1]);
-      st<T, NT>(Fk + 3 * S + b.n, (ZG && b.lo_y) ? fo[3] : fo[4]);
-      st<T, NT>(Fk + 4 * S + b.n, (ZG && b.hi_y) ? fo[4] : fo[3]);
-      st<T, NT>(Fk + 5 * S + b.n, (ZG && b.lo_z) ? fo[5] : fo[6]);
-      st<T, NT>(Fk + 6 * S + b.n, (ZG && b.hi_z) ? fo[6] : fo[5]);
+      st_pop<T, NT>(Fk + b.n, fo[0], hn, s0);
+      st_pop<T, NT>(Fk + 1 * S + b.n, (ZG && b.lo_x) ? fo[1] : fo[2], hn, s0 + 1);
+      st_pop<T, NT>(Fk + 2 * S + b.n, (ZG && b.hi_x) ? fo[2] : fo[1], hn, s0 + 2);
+      st_pop<T, NT>(Fk + 3 * S + b.n, (ZG && b.lo_y) ? fo[3] : fo[4], hn, s0 + 3);
+      st_pop<T, NT>(Fk + 4 * S + b.n, (ZG && b.hi_y) ? fo[4] : fo[3], hn, s0 + 4);
+      st_pop<T, NT>(Fk + 5 * S + b.n, (ZG && b.lo_z) ? fo[5] : fo[6], hn, s0 + 5);
+      st_pop<T, NT>(Fk + 6 * S + b.n, (ZG && b.hi_z) ? fo[6] : fo[5], hn, s0 + 6);
     } else {
       // slot i of the downstream cell x + c_i
-      st<T, NT>(Fk + b.n, fo[0]);
-      if (!(ZG && b.hi_x)) st<T, NT>(Fk + 1 * S + b.xp, fo[1]);
-      if (!(ZG && b.lo_x)) st<T, NT>(Fk + 2 * S + b.xm, fo[2]);
-      if (!(ZG && b.hi_y)) st<T, NT>(Fk + 3 * S + b.yp, fo[3]);
-      if (!(ZG && b.lo_y)) st<T, NT>(Fk + 4 * S + b.ym, fo[4]);
-      if (!(ZG && b.hi_z)) st<T, NT>(Fk + 5 * S + b.zp, fo[5]);
-      if (!(ZG && b.lo_z)) st<T, NT>(Fk + 6 * S + b.zm, fo[6]);
+      st_pop<T, NT>(Fk + b.n, fo[0], hn, s0);
+      if (!(ZG && b.hi_x)) st_pop<T, NT>(Fk + 1 * S + b.xp, fo[1], hxp, s0 + 1);
+      if (!(ZG && b.lo_x)) st_pop<T, NT>(Fk + 2 * S + b.xm, fo[2], hxm, s0 + 2);
+      if (!(ZG && b.hi_y)) st_pop<T, NT>(Fk + 3 * S + b.yp, fo[3], hyp, s0 + 3);
+      if (!(ZG && b.lo_y)) st_pop<T, NT>(Fk + 4 * S + b.ym, fo[4], hym, s0 + 4);
+      if (!(ZG && b.hi_z)) st_pop<T, NT>(Fk + 5 * S + b.zp, fo[5], hzp, s0 + 5);
+      if (!(ZG && b.lo_z)) st_pop<T, NT>(Fk + 6 * S + b.zm, fo[6], hzm, s0 + 6);
       if constexpr (ZG) {
         // ghost copy entering through a zero-gradient face
-        if (b.lo_x) st<T, NT>(Fk + 1 * S + b.n, fo[1]);
-        if (b.hi_x) st<T, NT>(Fk + 2 * S + b.n, fo[2]);
-        if (b.lo_y) st<T, NT>(Fk + 3 * S + b.n, fo[3]);
-        if (b.hi_y) st<T, NT>(Fk + 4 * S + b.n, fo[4]);
-        if (b.lo_z) st<T, NT>(Fk + 5 * S + b.n, fo[5]);
-        if (b.hi_z) st<T, NT>(Fk + 6 * S + b.n, fo[6]);
+        if (b.lo_x) st_pop<T, NT>(Fk + 1 * S + b.n, fo[1], hn, s0 + 1);
+        if (b.hi_x) st_pop<T, NT>(Fk + 2 * S + b.n, fo[2], hn, s0 + 2);
+        if (b.lo_y) st_pop<T, NT>(Fk + 3 * S + b.n, fo[3], hn, s0 + 3);
+        if (b.hi_y) st_pop<T, NT>(Fk + 4 * S + b.n, fo[4], hn, s0 + 4);
+        if (b.lo_z) st_pop<T, NT>(Fk + 5 * S + b.n, fo[5], hn, s0 + 5);
+        if (b.hi_z) st_pop<T, NT>(Fk + 6 * S + b.n, fo[6], hn, s0 + 6);
       }
     }
   }
@@ -447,7 +502,7 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
 template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool EDGES = true, bool SRC = false>
 __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g, const Coll& c, int n0,
                                                 bool act, int x, int y, int z, float* xs, float* vals,
-                                                const float* __restrict__ src = nullptr) {
+                                                uint32_t skey, const float* __restrict__ src = nullptr) {
   const int B = blockDim.x;
   const int lane = threadIdx.x;
   const Nbr b = make_nbr(g, x, y, z);
@@ -513,20 +568,31 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
       vals[8] = d.nonfinite;
     }
     if constexpr (SRC) add_source(f, src, (int64_t)g.nx * g.ny * g.nz, b.n);
+    // FP16 dither keys of the destination cells (the x slots are keyed by the cell
+    // that finally stores them, which is their destination as well)
+    uint32_t hn = 0u, hyp = 0u, hym = 0u, hzp = 0u, hzm = 0u;
+    if constexpr (sizeof(T) == 2) {
+      hn = cell_key(b.n, skey);
+      hyp = cell_key(b.yp, skey);
+      hym = cell_key(b.ym, skey);
+      hzp = cell_key(b.zp, skey);
+      hzm = cell_key(b.zm, skey);
+    }
 #pragma unroll
     for (int k = 0; k < kFields; ++k) {
       T* Fk = F + (int64_t)(7 * k) * S;
       const float* fo = f + 7 * k;
-      st<T, NT>(Fk + b.n, fo[0]);
-      if (!(ZG && b.hi_y)) st<T, NT>(Fk + 3 * S + b.yp, fo[3]);
-      if (!(ZG && b.lo_y)) st<T, NT>(Fk + 4 * S + b.ym, fo[4]);
-      if (!(ZG && b.hi_z)) st<T, NT>(Fk + 5 * S + b.zp, fo[5]);
-      if (!(ZG && b.lo_z)) st<T, NT>(Fk + 6 * S + b.zm, fo[6]);
+      const int s0 = 7 * k;
+      st_pop<T, NT>(Fk + b.n, fo[0], hn, s0);
+      if (!(ZG && b.hi_y)) st_pop<T, NT>(Fk + 3 * S + b.yp, fo[3], hyp, s0 + 3);
+      if (!(ZG && b.lo_y)) st_pop<T, NT>(Fk + 4 * S + b.ym, fo[4], hym, s0 + 4);
+      if (!(ZG && b.hi_z)) st_pop<T, NT>(Fk + 5 * S + b.zp, fo[5], hzp, s0 + 5);
+      if (!(ZG && b.lo_z)) st_pop<T, NT>(Fk + 6 * S + b.zm, fo[6], hzm, s0 + 6);
       if constexpr (ZG) {
-        if (b.lo_y) st<T, NT>(Fk + 3 * S + b.n, fo[3]);
-        if (b.hi_y) st<T, NT>(Fk + 4 * S + b.n, fo[4]);
-        if (b.lo_z) st<T, NT>(Fk + 5 * S + b.n, fo[5]);
-        if (b.hi_z) st<T, NT>(Fk + 6 * S + b.n, fo[6]);
+        if (b.lo_y) st_pop<T, NT>(Fk + 3 * S + b.n, fo[3], hn, s0 + 3);
+        if (b.hi_y) st_pop<T, NT>(Fk + 4 * S + b.n, fo[4], hn, s0 + 4);
+        if (b.lo_z) st_pop<T, NT>(Fk + 5 * S + b.n, fo[5], hn, s0 + 5);
+        if (b.hi_z) st_pop<T, NT>(Fk + 6 * S + b.n, fo[6], hn, s0 + 6);
       }
       w1[k * B] = fo[1];
       w2[k * B] = fo[2];
@@ -536,23 +602,26 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
       }
     }
     if (!hi && !in2) {
+      const uint32_t h = sizeof(T) == 2 ? cell_key(b.xp, skey) : 0u;
 #pragma unroll
-      for (int k = 0; k < kFields; ++k) st<T, NT>(F + (int64_t)(7 * k + 1) * S + b.xp, f[7 * k + 1]);
+      for (int k = 0; k < kFields; ++k) st_pop<T, NT>(F + (int64_t)(7 * k + 1) * S + b.xp, f[7 * k + 1], h, 7 * k + 1);
     }
     if (!lo && !in1) {
+      const uint32_t h = sizeof(T) == 2 ? cell_key(b.xm, skey) : 0u;
 #pragma unroll
-      for (int k = 0; k < kFields; ++k) st<T, NT>(F + (int64_t)(7 * k + 2) * S + b.xm, f[7 * k + 2]);
+      for (int k = 0; k < kFields; ++k) st_pop<T, NT>(F + (int64_t)(7 * k + 2) * S + b.xm, f[7 * k + 2], h, 7 * k + 2);
     }
   }
   __syncthreads();
   // write back the slots of this tile's cells whose reader/writer is in the tile
+  const uint32_t hown = (sizeof(T) == 2 && act) ? cell_key(b.n, skey) : 0u;
   if (act && in1) {
 #pragma unroll
-    for (int k = 0; k < kFields; ++k) st<T, NT>(F + (int64_t)(7 * k + 1) * S + b.n, s1[k * B + lane]);
+    for (int k = 0; k < kFields; ++k) st_pop<T, NT>(F + (int64_t)(7 * k + 1) * S + b.n, s1[k * B + lane], hown, 7 * k + 1);
   }
   if (act && in2) {
 #pragma unroll
-    for (int k = 0; k < kFields; ++k) st<T, NT>(F + (int64_t)(7 * k + 2) * S + b.n, s2[k * B + lane]);
+    for (int k = 0; k < kFields; ++k) st_pop<T, NT>(F + (int64_t)(7 * k + 2) * S + b.n, s2[k * B + lane], hown, 7 * k + 2);
   }
 }
 

@@ -37,6 +37,7 @@ struct StepLaunch {
   int lds;           // dynamic LDS bytes reserved per block (occupancy cap), 0 = none
   bool odd_lds;      // odd steps use k_step_odd_tiles (x populations shifted in LDS)
   const float* src;  // source of eq. 1, [5][N] per step, or nullptr (FP32 storage only)
+  uint32_t skey;     // step_key of the step (FP16 stochastic rounding)
 };
 
 constexpr int64_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit

@@ -72,14 +72,14 @@ __device__ void block_reduce_store(float vals[kDiagVals], float* __restrict__ ou
 // ------------------------------------------------------------------ the update
 template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC = false>
 __global__ void __launch_bounds__(1024) k_step(T* __restrict__ F, Grid g, Coll c, float* __restrict__ partials,
-                                                const float* __restrict__ src) {
+                                                const float* __restrict__ src, uint32_t skey) {
   const CellPos pos = block_cell(g);
   float vals[kDiagVals];
   if constexpr (DIAG) {
 #pragma unroll
     for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
   }
-  if (pos.active) cell_update<ODD, COLL, T, ZG, DIAG, NT, SRC>(F, g, c, pos.x, pos.y, pos.z, vals, src);
+  if (pos.active) cell_update<ODD, COLL, T, ZG, DIAG, NT, SRC>(F, g, c, pos.x, pos.y, pos.z, vals, skey, src);
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(1024) k_step(T* __restrict__ F, Grid g, Coll c
 template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool ROWS, bool SRC = false>
 __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid g, Coll c,
                                                           float* __restrict__ partials,
-                                                          const float* __restrict__ src) {
+                                                          const float* __restrict__ src, uint32_t skey) {
   extern __shared__ float xs[];
   int n0, x = 0, y = 0, z = 0;
   bool act;
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid
 #pragma unroll
     for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
   }
-  tile_update_odd<COLL, T, ZG, DIAG, NT, !ROWS, SRC>(F, g, c, n0, act, x, y, z, xs, vals, src);
+  tile_update_odd<COLL, T, ZG, DIAG, NT, !ROWS, SRC>(F, g, c, n0, act, x, y, z, xs, vals, skey, src);
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
@@ -281,15 +281,15 @@ static hipError_t launch_step_nt(const StepLaunch& L, hipStream_t s) {
     const OddTiles ot = odd_tiles(g);
     if (ot.rows)
       hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, true, SRC>), dim3((unsigned)ot.blocks),
-                         dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src);
+                         dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src, L.skey);
     else
       hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, false, SRC>), dim3((unsigned)ot.blocks),
-                         dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src);
+                         dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src, L.skey);
     return hipGetLastError();
   }
   const int64_t blocks = step_blocks(g, L.block);
   hipLaunchKernelGGL((k_step<ODD, COLL, T, ZG, DIAG, NT, SRC>), dim3((unsigned)blocks), dim3(L.block), L.lds, s,
-                     F, g, L.c, L.partials, L.src);
+                     F, g, L.c, L.partials, L.src, L.skey);
   return hipGetLastError();
 }
 

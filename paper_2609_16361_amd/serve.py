@@ -85,7 +85,7 @@ class Server:
 
     def __init__(self, backend, arena_bytes: int, max_active_cells: int | None = None,
                  chunk_steps: int = 50, result_handler=None, clock=time.perf_counter,
-                 sync=None, max_instances: int = 4096):
+                 sync=None, max_instances: int = 4096, storage_override: int | None = None):
         self.b = backend
         self.arena_bytes = int(arena_bytes)
         self.max_cells = max_active_cells
@@ -94,10 +94,13 @@ class Server:
         self.clock = clock
         self.sync = sync or (lambda: None)
         self.max_instances = max_instances
+        # None: each request's own storage; else every request in this storage
+        self.storage_override = storage_override
 
     def serve(self, requests) -> ServeStats:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        out = {r.rid: Outcome(r.rid, r.kind, r.storage, r.case.cells, r.steps, r.arrival) for r in reqs}
+        stg = {r.rid: (r.storage if self.storage_override is None else self.storage_override) for r in reqs}
+        out = {r.rid: Outcome(r.rid, r.kind, stg[r.rid], r.case.cells, r.steps, r.arrival) for r in reqs}
         pending = list(reqs)
         active = {}                 # instance id -> (request, bytes)
         used_bytes = 0
@@ -109,7 +112,7 @@ class Server:
             # admission: arrived requests in order while memory and the cell cap allow
             while pending and pending[0].arrival <= now:
                 r = pending[0]
-                nb = state_bytes(r.case.params, r.storage)
+                nb = state_bytes(r.case.params, stg[r.rid])
                 if nb > self.arena_bytes:
                     out[r.rid].ok = False        # can never fit: rejected
                     out[r.rid].completed = now
@@ -120,7 +123,7 @@ class Server:
                 if self.max_cells is not None and active and used_cells + r.case.cells > self.max_cells:
                     break
                 try:
-                    iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=r.storage)
+                    iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=stg[r.rid])
                 except RuntimeError as e:
                     # no free run of that size yet (fragmentation): wait for retirements
                     if getattr(e, "status", None) == ENOMEM and active:

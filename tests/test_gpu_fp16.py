@@ -1,9 +1,10 @@
 """FP16 population storage (shifted by w_i Q_ref and scaled per field by a power
 of two) with FP32 moments, reconstruction and collision, against the FP64 oracle.
 
-Tolerance: each stored value is rounded to FP16 (relative step 2^-11 = 4.9e-4 of
-the field's largest shifted population, after the exact power-of-two scaling) at
-every store; a handful of steps therefore stays within a few such steps, and the
+Tolerance: each stored value is rounded stochastically to FP16 (after the exact
+power-of-two scaling), so a store errs by less than one FP16 ulp, a relative
+2^-10 = 9.8e-4 of the field's largest shifted population, with zero mean; a
+handful of steps therefore stays within a few such ulps per step, and the
 conserved fields after 100 smooth steps within about 1e-3 relative L2.
 """
 import math
@@ -48,7 +49,7 @@ def test_fp16_tiny_grids(dims, bc):
             sl = slice(7 * k, 7 * k + 7)
             err = np.abs(g_gpu[sl] - g_ora[sl]).max() / np.abs(g_ora[sl]).max()
             say(f"   field {k}: {err:.2e}")
-            assert err <= 4 * 2.0 ** -11 * steps, (dims, steps, k, err)
+            assert err <= 4 * 2.0 ** -10 * steps, (dims, steps, k, err)
 
 
 def test_fp16_vortex_100_steps():
