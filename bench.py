@@ -420,7 +420,8 @@ def main():
                                f"Re 1600, regularized collision + sensor, diagnostics every "
                                f"{args.diag_every} steps",
                    "cells": cells, "steps": args.steps, "diag_every": args.diag_every,
-                   "block": args.block or (256 if args.fp16 else 1024),
+                   "block": args.block or 256,
+                   "blocks_per_cu": 0 if args.fp16 else 4,
                    "nontemporal": True if args.nontemporal is None else bool(args.nontemporal),
                    "odd_lds": bool(args.odd_lds),
                    "parallelism": "single GPU"},

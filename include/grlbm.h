@@ -156,10 +156,10 @@ lbm_status lbm_get_populations(lbm_ctx* ctx, float* f, int64_t* step);
 lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
 
 /* Launch shape of the collide-and-stream kernels: `block` threads per block (a
- * multiple of 64 in [64, 1024]; default 1024 for FP32 storage and 256 for FP16),
- * nontemporal loads/stores on or off (default on), and an occupancy cap of
- * `blocks_per_cu` resident blocks per compute unit (1..32, enforced by reserving
- * LDS; 0 = no cap, the default).  With `odd_lds` = 1 (the default) the odd AA step
+ * multiple of 64 in [64, 1024]; default 256), nontemporal loads/stores on or off
+ * (default on), and an occupancy cap of `blocks_per_cu` resident blocks per compute
+ * unit (1..32, enforced by reserving LDS; 0 = no cap; default 4 for FP32 storage and
+ * no cap for FP16).  With `odd_lds` = 1 (the default) the odd AA step
  * moves the +-x populations through LDS so that all its HBM accesses are aligned;
  * it runs one block per x-row when nx <= 1024 and tiles of 256 consecutive cells
  * otherwise, and `block` and `blocks_per_cu` then apply to the even step only.

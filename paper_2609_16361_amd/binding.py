@@ -296,15 +296,16 @@ class Solver:
 
     def __init__(self, params: dict, stream: int | None = None, storage: int | None = None,
                  block: int | None = None, nontemporal: bool | None = None, layout_pad: int = 0,
-                 blocks_per_cu: int = 0, odd_lds: bool = True):
+                 blocks_per_cu: int | None = None, odd_lds: bool = True):
         self.params = dict(params)
         self.cparams = make_params(params, storage=storage, layout_pad=layout_pad)
         self.shape = (self.cparams.nz, self.cparams.ny, self.cparams.nx)
         self.ctx = lbm_create(self.cparams, stream)
-        if block is not None or nontemporal is not None or blocks_per_cu or not odd_lds:
-            default_block = 256 if self.cparams.storage == LBM_STORE_F16 else 1024
-            lbm_set_launch(self.ctx, block or default_block, True if nontemporal is None else bool(nontemporal),
-                           blocks_per_cu, odd_lds)
+        if block is not None or nontemporal is not None or blocks_per_cu is not None or not odd_lds:
+            # unspecified settings keep the library's defaults
+            default_bpc = 0 if self.cparams.storage == LBM_STORE_F16 else 4
+            lbm_set_launch(self.ctx, block or 256, True if nontemporal is None else bool(nontemporal),
+                           default_bpc if blocks_per_cu is None else blocks_per_cu, odd_lds)
 
     def init(self, Q):
         lbm_init_fields(self.ctx, np.asarray(Q, dtype=np.float64).reshape((5,) + self.shape))

@@ -194,6 +194,7 @@ namespace {
 
 constexpr int kDiagVals = 9;
 constexpr int32_t kRingCap = 1024;
+constexpr int kDefaultBlocksPerCuF32 = 4;
 
 }  // namespace
 
@@ -210,7 +211,7 @@ struct lbm_ctx {
   bool own_F = false;
   int64_t step = 0;
   bool ready = false;
-  int block = 1024;
+  int block = 256;
   bool nt = true;
   int lds = 0;
   bool odd_lds = true;
@@ -225,9 +226,18 @@ struct lbm_ctx {
 
 namespace {
 
+// LDS reserved per block so that at most blocks_per_cu blocks are resident per CU:
+// just over 1/(blocks_per_cu + 1) of the 160 KB of a CU (0 = no cap).
+int lds_for_blocks_per_cu(int blocks_per_cu) {
+  if (blocks_per_cu <= 0) return 0;
+  const int lds = (int)(grlbm::kLdsPerCU / (blocks_per_cu + 1)) + 256;
+  return lds > 65536 ? 65536 : lds;
+}
+
 lbm_status ensure_partials(lbm_ctx* c) {
   // partials for the larger of the two launch shapes (even step, LDS odd step)
-  const int64_t nb = std::max(grlbm::step_blocks(c->g, c->block), grlbm::odd_tiles(c->g).blocks);
+  const int64_t nb = std::max(grlbm::step_blocks(c->g, c->block),
+                              grlbm::odd_tiles(c->g, c->p.storage == LBM_STORE_F16).blocks);
   if (nb <= c->partials_blocks) return LBM_OK;
   if (c->partials) HIP_TRY(hipFree(c->partials));
   c->partials = nullptr;
@@ -271,9 +281,12 @@ lbm_status create_common(const lbm_params* p, void* buf, size_t bytes, void* str
   c->g = make_grid(p);
   c->c = make_coll(p);
   c->F_bytes = state_bytes(p);
-  // FP16 loads move half the bytes per instruction: fully used 256-thread blocks
-  // keep more of them in flight than the FP32 default of 1024 (measured ~2%)
-  if (p->storage == LBM_STORE_F16) c->block = 256;
+  // Default launch of the even step: 256-thread blocks; FP32 capped at 4 resident
+  // blocks (16 waves) per CU, FP16 (two-byte loads keep fewer bytes in flight per
+  // wave) uncapped -- the fastest shapes in continuous-run A/B timing on MI355X for
+  // both short (256-cell) and long (1024- and 4096-cell) rows.
+  c->block = 256;
+  c->lds = p->storage == LBM_STORE_F16 ? 0 : lds_for_blocks_per_cu(kDefaultBlocksPerCuF32);
   auto bail = [&](lbm_status s) {
     lbm_destroy(c);
     return s;
@@ -343,9 +356,7 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t nontemporal, int32_
   c->block = block;
   c->nt = nontemporal != 0;
   c->odd_lds = odd_lds != 0;
-  // reserve just over 1/(blocks_per_cu + 1) of the 160 KB LDS of a CU per block
-  c->lds = blocks_per_cu > 0 ? (int)(grlbm::kLdsPerCU / (blocks_per_cu + 1)) + 256 : 0;
-  if (c->lds > 65536) c->lds = 65536;
+  c->lds = lds_for_blocks_per_cu(blocks_per_cu);
   return LBM_OK;
 }
 

@@ -41,18 +41,19 @@ struct StepLaunch {
 };
 
 constexpr int64_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
-constexpr int kOddTile = 256;              // cells per linear tile of k_step_odd_tiles
+constexpr int kOddTileF32 = 512;           // cells per linear tile of k_step_odd_tiles, FP32
+constexpr int kOddTileF16 = 256;           // the same for FP16 storage
 constexpr int kMaxRowTile = 1024;          // longest x-row k_step_odd_tiles maps to one block
 
 hipError_t launch_step(const StepLaunch& L, hipStream_t s);
 int64_t step_blocks(const Grid& g, int block);
 struct OddTiles {
-  bool rows;       // one block per x-row, else linear tiles of kOddTile cells
+  bool rows;       // one block per x-row, else linear tiles of kOddTileF32/F16 cells
   int block;       // threads per block
   int64_t blocks;  // blocks (= diagnostic partials)
   int lds;         // dynamic LDS bytes per block
 };
-OddTiles odd_tiles(const Grid& g);          // launch shape of k_step_odd_tiles
+OddTiles odd_tiles(const Grid& g, bool f16);  // launch shape of k_step_odd_tiles
 int64_t launch_blocks(const StepLaunch& L);  // blocks (= diagnostic partials) of a launch
 hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s);
 hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const double* Q, int64_t N,

@@ -278,7 +278,7 @@ static hipError_t launch_step_nt(const StepLaunch& L, hipStream_t s) {
   const Grid& g = L.g;
   T* F = (T*)L.F;
   if (ODD && L.odd_lds) {
-    const OddTiles ot = odd_tiles(g);
+    const OddTiles ot = odd_tiles(g, L.f16);
     if (ot.rows)
       hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, true, SRC>), dim3((unsigned)ot.blocks),
                          dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src, L.skey);
@@ -334,17 +334,21 @@ int64_t step_blocks(const Grid& g, int block) {
 }
 
 // Launch shape of k_step_odd_tiles: one block per x-row when a row fits in a block
-// (no index division, no tile edge inside a row), else linear tiles of kOddTile
-// cells.  The dynamic LDS holds the two x slots of a tile and a sink column (15
-// floats per cell), padded so that about 16 waves are resident per CU, where the
-// odd step's sustained bandwidth peaks.
-OddTiles odd_tiles(const Grid& g) {
+// (no index division, no tile edge inside a row), else linear tiles.  The dynamic
+// LDS holds the two x slots of a tile and a sink column (15 floats per cell),
+// padded to cap the resident waves per CU where the odd step's sustained bandwidth
+// peaked in continuous-run A/B timing on MI355X: FP32 row blocks at 8 waves per CU,
+// FP32 linear tiles of 512 cells at 16; FP16 (two-byte loads keep fewer bytes in
+// flight per wave) row blocks and 256-cell tiles at 16.
+OddTiles odd_tiles(const Grid& g, bool f16) {
   OddTiles t;
   t.rows = g.nx <= kMaxRowTile;
-  t.block = t.rows ? (g.nx + 63) / 64 * 64 : kOddTile;
-  t.blocks = t.rows ? (int64_t)g.ny * g.nz : ((int64_t)g.nx * g.ny * g.nz + kOddTile - 1) / kOddTile;
+  const int tile = f16 ? kOddTileF16 : kOddTileF32;
+  t.block = t.rows ? (g.nx + 63) / 64 * 64 : tile;
+  t.blocks = t.rows ? (int64_t)g.ny * g.nz : ((int64_t)g.nx * g.ny * g.nz + tile - 1) / tile;
+  const int waves = (t.rows && !f16) ? 8 : 16;
   const int need = 15 * (int)sizeof(float) * t.block;
-  const int per_cu = 1024 / t.block > 1 ? 1024 / t.block : 1;
+  const int per_cu = waves * 64 / t.block > 1 ? waves * 64 / t.block : 1;
   int lds = (int)(kLdsPerCU / (per_cu + 1)) + 256;
   if (lds > 65536) lds = 65536;
   t.lds = lds > need ? lds : need;
@@ -352,7 +356,7 @@ OddTiles odd_tiles(const Grid& g) {
 }
 
 int64_t launch_blocks(const StepLaunch& L) {
-  return L.odd && L.odd_lds ? odd_tiles(L.g).blocks : step_blocks(L.g, L.block);
+  return L.odd && L.odd_lds ? odd_tiles(L.g, L.f16).blocks : step_blocks(L.g, L.block);
 }
 
 hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s) {
