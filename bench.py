@@ -73,7 +73,7 @@ def becker_linf(case, Q):
 
 def bench_batch(count=64, steps=5000, seed=0, stream=None):
     """Batched Becker shocks (seeded lengths 512-8192 x 4 x 4, Mach 1.5-5, FP32,
-    regularized collision with sensor): autotuned persistent kernel + graphs, against
+    regularized collision with sensor): autotuned batch kernel + graphs, against
     the same solves run one after another in single contexts."""
     import numpy as np
     import torch

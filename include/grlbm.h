@@ -200,7 +200,8 @@ typedef struct {
   int32_t block;          /* threads per block = cells per tile (64..1024)         */
   int32_t nontemporal;    /* nontemporal loads and stores                          */
   int32_t blocks_per_cu;  /* occupancy cap enforced by an LDS reservation (0 = off) */
-  int32_t grid;           /* persistent grid size in blocks                        */
+  int32_t grid;           /* blocks that loop over the tiles (persistent), or 0 for
+                             one block per tile                                     */
 } lbm_batch_tuning;
 
 typedef struct {
@@ -247,7 +248,8 @@ lbm_status lbm_batch_remove(lbm_batch* b, int32_t id);
 /* Occupancy and tuning summary. */
 lbm_status lbm_batch_info(lbm_batch* b, lbm_batch_stats* out);
 
-/* Set the launch shape (invalidates the captured graph).  EINVAL on bad values,
+/* Set the launch shape (invalidates the captured graph).  grid 0 launches one block
+ * per tile of each group (rounded up to a multiple of 256).  EINVAL on bad values,
  * ENOMEM if the tile width needs more tiles than the capacity. */
 lbm_status lbm_batch_set_tuning(lbm_batch* b, const lbm_batch_tuning* t);
 

@@ -4,7 +4,7 @@ The library holds every kernel of the solver and the C ABI of include/grlbm.h.
 Packed-FP32 instructions are disabled for all device code.  Multiply-adds are
 fused only inside one source expression (-ffp-contract=on): the collision is
 inlined into several kernels (the two AA parities, the row-staged odd step, the
-batched persistent kernel) and with the compiler's default cross-statement fusion
+batch kernel) and with the compiler's default cross-statement fusion
 each copy could round differently; this way every kernel computes a cell update
 with the same FP32 operations and the paths agree bit for bit.
 """

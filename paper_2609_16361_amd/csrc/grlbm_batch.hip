@@ -3,15 +3,17 @@
 // One device arena holds the populations of every instance (the same SoA, AA
 // in-place layout as a single context).  A descriptor table and a tile work-list
 // live in device memory: a tile is one block-width range of consecutive cells of
-// one instance.  k_batch_step is a persistent kernel: a fixed grid loops over the tile
-// list, and each block derives its instance's AA parity and whether it is active
-// from a device-resident clock, so one launch advances every active instance by one
-// step whatever its size, boundaries, parameters or age.  Consecutive launches on
-// one stream order the steps (no grid-wide barrier is needed).  Time loops of K
-// steps are captured once in a hipGraph: K step nodes per (collision, storage)
-// group followed by a one-lane kernel that advances the clock (no memset nodes),
-// and replayed; the tile list, descriptors and tile count can change between
-// replays because the graph only holds their addresses.
+// one instance.  k_batch_step loops over the tile list with a fixed grid
+// (persistent) or takes one tile per block (grid 0 in the tuning), and each block
+// derives its instance's AA parity and whether it is active from a device-resident
+// clock, so one launch advances every active instance by one step whatever its
+// size, boundaries, parameters or age.  Consecutive launches on one stream order
+// the steps (no grid-wide barrier is needed).  Time loops of K steps are captured
+// once in a hipGraph: K step nodes per (collision, storage) group followed by a
+// one-lane kernel that advances the clock (no memset nodes), and replayed; the tile
+// list, descriptors and tile count can change between replays because the graph
+// only holds their addresses (with one block per tile, a change of the rounded
+// grid captures the graph again).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -151,6 +153,7 @@ struct lbm_batch {
   int32_t ntiles_host[kGroups] = {0, 0, 0, 0};
   hipGraphExec_t graph = nullptr;
   unsigned graph_groups = 0;  // bitmask of groups captured
+  int32_t graph_grid[kGroups] = {0, 0, 0, 0};  // launch grids baked into the graph
 };
 
 namespace {
@@ -199,9 +202,21 @@ unsigned active_groups(const lbm_batch* b) {
   return m;
 }
 
+// Blocks launched for group g.  A fixed grid loops over the tiles (persistent); grid
+// 0 gives every tile its own block, rounded up to a multiple of kGridQuantum so
+// that small changes of the tile count keep a captured graph (the extra blocks
+// find no tile and exit).
+constexpr int32_t kGridQuantum = 256;
+
+int32_t launch_grid(const lbm_batch* b, int g) {
+  if (b->tune.grid > 0) return b->tune.grid;
+  const int32_t n = std::max<int32_t>(b->ntiles_host[g], 1);
+  return (n + kGridQuantum - 1) / kGridQuantum * kGridQuantum;
+}
+
 template <int COLL, typename T>
 hipError_t launch_group_t(lbm_batch* b, int g, int32_t j) {
-  const dim3 grid((unsigned)b->tune.grid), block((unsigned)b->tune.block);
+  const dim3 grid((unsigned)launch_grid(b, g)), block((unsigned)b->tune.block);
   T* arena = reinterpret_cast<T*>(b->arena);
   const BatchTile* tiles = b->d_tiles + (size_t)g * b->max_tiles;
   const int32_t* nt = b->d_ntiles + g;
@@ -261,7 +276,16 @@ lbm_status capture_graph(lbm_batch* b, unsigned groups) {
     return fail(LBM_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
   }
   b->graph_groups = groups;
+  for (int k = 0; k < kGroups; ++k) b->graph_grid[k] = launch_grid(b, k);
   return LBM_OK;
+}
+
+// The captured graph no longer matches the groups to step or their launch grids.
+bool graph_stale(const lbm_batch* b, unsigned groups) {
+  if (!b->graph || b->graph_groups != groups) return true;
+  for (int k = 0; k < kGroups; ++k)
+    if ((groups & (1u << k)) && b->graph_grid[k] != launch_grid(b, k)) return true;
+  return false;
 }
 
 lbm_status run_steps(lbm_batch* b, int64_t n) {
@@ -279,7 +303,7 @@ lbm_status run_steps(lbm_batch* b, int64_t n) {
   }
   int64_t left = n;
   if (b->graph_steps > 1 && left >= b->graph_steps) {
-    if (!b->graph || b->graph_groups != groups) {
+    if (graph_stale(b, groups)) {
       st = capture_graph(b, groups);
       if (st != LBM_OK) return st;
     }
@@ -396,10 +420,12 @@ lbm_status lbm_batch_create(size_t arena_bytes, int32_t max_instances, int32_t m
       hipStreamSynchronize(b->stream) != hipSuccess)
     return bail(fail(LBM_EDEVICE, "batch table initialisation failed"));
   b->graph_steps = graph_steps;
-  b->tune.block = 256;
+  // one 512-cell tile per block: the fastest shape on the Becker batch and the
+  // serving mix (persistent grids trail it by 6-9%)
+  b->tune.block = 512;
   b->tune.nontemporal = 1;
   b->tune.blocks_per_cu = 0;
-  b->tune.grid = b->num_cus * 4;
+  b->tune.grid = 0;
   *out = b;
   return LBM_OK;
 }
@@ -573,7 +599,7 @@ lbm_status lbm_batch_set_tuning(lbm_batch* b, const lbm_batch_tuning* t) {
   if (!b || !t) return fail(LBM_EINVAL, "NULL argument");
   if (t->block < 64 || t->block > 1024 || t->block % 64 != 0)
     return fail(LBM_EINVAL, "block = %d must be a multiple of 64 in [64, 1024]", t->block);
-  if (t->grid < 1 || t->grid > (1 << 24)) return fail(LBM_EINVAL, "grid = %d outside [1, 2^24]", t->grid);
+  if (t->grid < 0 || t->grid > (1 << 24)) return fail(LBM_EINVAL, "grid = %d outside [0, 2^24]", t->grid);
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > 32) return fail(LBM_EINVAL, "blocks_per_cu outside [0, 32]");
   if (t->block != b->tune.block) {
     // the tile width is the block width: check the capacity before switching
@@ -619,6 +645,16 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_batch_tunin
         t.grid = b->num_cus * bpc;
         cands.push_back(t);
       }
+    }
+  // one block per tile, occupancy set by the registers alone
+  for (int block : {128, 256, 512, 1024})
+    for (int nt : {0, 1}) {
+      lbm_batch_tuning t{};
+      t.block = block;
+      t.nontemporal = nt;
+      t.blocks_per_cu = 0;
+      t.grid = 0;
+      cands.push_back(t);
     }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   lbm_status st = LBM_OK;

@@ -1,5 +1,5 @@
 """GPU tests of the batched path (lbm_batch_*): uneven instances stepped by one
-persistent kernel over a tile work-list, time loops replayed from a captured graph.
+kernel launch over a tile work-list, time loops replayed from a captured graph.
 
 The bar is bitwise: an instance inside a batch must end exactly where the same
 instance run alone in a context (lbm_create/lbm_step) ends, whatever the other
@@ -42,12 +42,23 @@ def mix():
     return cases
 
 
-@pytest.mark.parametrize("graph_steps", [1, 16])
-def test_batch_equals_single_contexts_bitwise(graph_steps):
-    cases = mix()
-    steps = [37, 20, 41, 25, 30, 18]
-    admit = [0, 0, 5, 9, 9, 23]          # clock at which each instance joins
+# launch shapes: (block, nontemporal, blocks_per_cu, grid); None keeps the default.
+# grid 0 is one block per tile: the 36864-cell instance takes its group past 256
+# tiles of 128 cells and back, so the rounded grid changes and the graph is
+# captured again on the way.
+SHAPES = [(1, None), (16, None), (16, (512, 1, 0, 0)), (16, (128, 0, 0, 0)), (1, (128, 1, 0, 0)),
+          (16, (256, 0, 4, 7))]
+
+
+@pytest.mark.parametrize("graph_steps,shape", SHAPES)
+def test_batch_equals_single_contexts_bitwise(graph_steps, shape):
+    cases = mix() + [(inputs.random_smooth(48, 32, 24, seed=5, amp=0.05), None)]
+    steps = [37, 20, 41, 25, 30, 18, 12]
+    admit = [0, 0, 5, 9, 9, 23, 9]       # clock at which each instance joins
     with binding.Batch(1 << 26, graph_steps=graph_steps) as b:
+        if shape is not None:
+            b.set_tuning(*shape)
+            assert b.info()["tuning"] == dict(zip(("block", "nontemporal", "blocks_per_cu", "grid"), shape))
         ids = {}
         clock = 0
         for t_admit in sorted(set(admit)):
