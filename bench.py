@@ -311,6 +311,10 @@ def main():
     ap.add_argument("--diag-every", type=int, default=50)
     ap.add_argument("--block", type=int, default=None)
     ap.add_argument("--nontemporal", type=int, default=None)
+    ap.add_argument("--autotune", type=int, default=0, metavar="STEPS",
+                    help="time the launch shapes for STEPS steps each before the run and keep the fastest")
+    ap.add_argument("--blocks-per-cu", type=int, default=None,
+                    help="even-step occupancy cap in blocks per CU (0 = none; default 4 FP32, none FP16)")
     ap.add_argument("--layout-pad", type=int, default=0)
     ap.add_argument("--odd-lds", type=int, default=1,
                     help="1: odd step shifts the +-x populations in LDS (default); 0: direct")
@@ -371,13 +375,19 @@ def main():
     bytes_per_lup = BYTES_PER_LUP_F32 / 2 if args.fp16 else BYTES_PER_LUP_F32
     solver = binding.Solver(case.params, stream=stream.cuda_stream, block=args.block,
                             nontemporal=None if args.nontemporal is None else bool(args.nontemporal),
-                            layout_pad=args.layout_pad, storage=storage, odd_lds=bool(args.odd_lds))
+                            layout_pad=args.layout_pad, storage=storage, odd_lds=bool(args.odd_lds),
+                            blocks_per_cu=args.blocks_per_cu)
     solver.init(case.Q0)
     del case.Q0
 
     solver.step(args.warmup, args.diag_every)
     torch.cuda.synchronize()
     solver.diagnostics()
+    tuned = None
+    if args.autotune:
+        best, best_us, tried = solver.autotune(trial_steps=args.autotune)
+        tuned = {"us_per_step": round(best_us, 2), "candidates": len(tried)}
+    launch = solver.launch()
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -393,6 +403,8 @@ def main():
     recs, status = solver.diagnostics()
     assert status == binding.LBM_OK and all(r["nonfinite"] == 0 for r in recs), "state diverged"
     solver.close()
+    if tuned is not None:
+        launch["autotuned"] = tuned
 
     glups = cells * args.steps / (ms * 1e-3) / 1e9
     avg_launch_ms = ms / args.steps
@@ -420,10 +432,7 @@ def main():
                                f"Re 1600, regularized collision + sensor, diagnostics every "
                                f"{args.diag_every} steps",
                    "cells": cells, "steps": args.steps, "diag_every": args.diag_every,
-                   "block": args.block or 256,
-                   "blocks_per_cu": 0 if args.fp16 else 4,
-                   "nontemporal": True if args.nontemporal is None else bool(args.nontemporal),
-                   "odd_lds": bool(args.odd_lds),
+                   **launch,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),

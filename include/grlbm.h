@@ -161,11 +161,35 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
  * unit (1..32, enforced by reserving LDS; 0 = no cap; default 4 for FP32 storage and
  * no cap for FP16).  With `odd_lds` = 1 (the default) the odd AA step
  * moves the +-x populations through LDS so that all its HBM accesses are aligned;
- * it runs one block per x-row when nx <= 1024 and tiles of 256 consecutive cells
- * otherwise, and `block` and `blocks_per_cu` then apply to the even step only.
+ * it runs one block per x-row when nx <= 1024 and otherwise tiles of 512
+ * consecutive cells (256 for FP16), and `block` and `blocks_per_cu` then apply to
+ * the even step only.
  * Results do not depend on any of these settings.  EINVAL otherwise. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t nontemporal, int32_t blocks_per_cu,
                           int32_t odd_lds);
+
+/* A launch shape as lbm_set_launch takes it. */
+typedef struct {
+  int32_t block, nontemporal, blocks_per_cu, odd_lds;
+} lbm_launch;
+
+/* The context's current launch shape. */
+lbm_status lbm_get_launch(lbm_ctx* ctx, lbm_launch* out);
+
+/* Time candidate launch shapes on the context's live state and keep the fastest:
+ * even-step blocks of 256 (capped at 4, 2 or no blocks per CU), 512 (2 or none) and
+ * 1024 threads, each with nontemporal access on and off, the LDS odd step on.  Each
+ * trial runs 2 warm-up steps and trial_steps timed steps (rounded up to even) with
+ * no diagnostics; the populations and the step count are restored from a device
+ * snapshot after each trial, so the state after the call is bitwise the state
+ * before it.  The fastest shape differs with the grid (the nontemporal hint costs
+ * up to a third of the rate on some states of a few hundred MB and gains 3-8% on
+ * larger ones).  best/best_us receive it and its time per step; up to max_tried
+ * (shape, time) pairs go to tried/tried_us (may be NULL), their number to ntried.
+ * Needs a second buffer of the population size (ENOMEM if it cannot be had);
+ * synchronises the stream; ESTATE before initialisation, EINVAL if trial_steps < 2. */
+lbm_status lbm_autotune(lbm_ctx* ctx, int32_t trial_steps, lbm_launch* best, float* best_us, lbm_launch* tried,
+                        float* tried_us, int32_t max_tried, int32_t* ntried);
 
 /* Source term S of eq. 1 for the following steps: S_dev points to device memory
  * S[5][nz][ny][nx] (FP32, lattice units per step, field order rho, rho u_x,

@@ -49,6 +49,15 @@ class lbm_diag(ctypes.Structure):
     ]
 
 
+class lbm_launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("odd_lds", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(block=self.block, nontemporal=self.nontemporal,
+                    blocks_per_cu=self.blocks_per_cu, odd_lds=self.odd_lds)
+
+
 class lbm_batch_tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("grid", ctypes.c_int32)]
@@ -96,6 +105,9 @@ SIGNATURES = {
     "lbm_get_populations": (ctypes.c_int, [_vp, _P(ctypes.c_float), _P(ctypes.c_int64)]),
     "lbm_set_populations": (ctypes.c_int, [_vp, _P(ctypes.c_float), ctypes.c_int64]),
     "lbm_set_launch": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbm_get_launch": (ctypes.c_int, [_vp, _P(lbm_launch)]),
+    "lbm_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _P(lbm_launch), _P(ctypes.c_float), _P(lbm_launch),
+                                    _P(ctypes.c_float), ctypes.c_int32, _P(ctypes.c_int32)]),
     "lbm_set_source": (ctypes.c_int, [_vp, _vp]),
     "lbm_mms_source": (ctypes.c_int, [_P(lbm_mms), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_double, _vp, _vp]),
@@ -285,6 +297,24 @@ def lbm_mms_source(m: dict, nx: int, ny: int, nz: int, t: float, S_dev: int, str
            "lbm_mms_source")
 
 
+def lbm_get_launch(ctx: int) -> dict:
+    out = lbm_launch()
+    _check(load().lbm_get_launch(ctx, ctypes.byref(out)), "lbm_get_launch")
+    return out.as_dict()
+
+
+def lbm_autotune(ctx: int, trial_steps: int = 20, max_tried: int = 32):
+    """Returns (best launch dict, best us/step, [(launch dict, us/step), ...])."""
+    best = lbm_launch()
+    bus = ctypes.c_float(0)
+    tried = (lbm_launch * max_tried)()
+    tus = (ctypes.c_float * max_tried)()
+    n = ctypes.c_int32(0)
+    _check(load().lbm_autotune(ctx, int(trial_steps), ctypes.byref(best), ctypes.byref(bus), tried, tus,
+                               int(max_tried), ctypes.byref(n)), "lbm_autotune")
+    return best.as_dict(), bus.value, [(tried[i].as_dict(), tus[i]) for i in range(n.value)]
+
+
 def lbm_last_error() -> str:
     return load().lbm_last_error().decode(errors="replace")
 
@@ -315,6 +345,13 @@ class Solver:
 
     def set_source(self, S_dev):
         lbm_set_source(self.ctx, S_dev)
+
+    def autotune(self, trial_steps=20):
+        """Pick the fastest launch shape on the current state (left unchanged)."""
+        return lbm_autotune(self.ctx, trial_steps)
+
+    def launch(self):
+        return lbm_get_launch(self.ctx)
 
     def moments(self):
         return lbm_moments(self.ctx, self.shape)

@@ -213,6 +213,7 @@ struct lbm_ctx {
   bool ready = false;
   int block = 256;
   bool nt = true;
+  int bpc = 0;  // occupancy cap of the even step (0 = none), enforced through lds
   int lds = 0;
   bool odd_lds = true;
   const float* src = nullptr;  // caller-owned source of eq. 1, [5][N] FP32, or nullptr
@@ -286,7 +287,8 @@ lbm_status create_common(const lbm_params* p, void* buf, size_t bytes, void* str
   // wave) uncapped -- the fastest shapes in continuous-run A/B timing on MI355X for
   // both short (256-cell) and long (1024- and 4096-cell) rows.
   c->block = 256;
-  c->lds = p->storage == LBM_STORE_F16 ? 0 : lds_for_blocks_per_cu(kDefaultBlocksPerCuF32);
+  c->bpc = p->storage == LBM_STORE_F16 ? 0 : kDefaultBlocksPerCuF32;
+  c->lds = lds_for_blocks_per_cu(c->bpc);
   auto bail = [&](lbm_status s) {
     lbm_destroy(c);
     return s;
@@ -356,7 +358,106 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t block, int32_t nontemporal, int32_
   c->block = block;
   c->nt = nontemporal != 0;
   c->odd_lds = odd_lds != 0;
+  c->bpc = blocks_per_cu;
   c->lds = lds_for_blocks_per_cu(blocks_per_cu);
+  return LBM_OK;
+}
+
+lbm_status lbm_get_launch(lbm_ctx* c, lbm_launch* out) {
+  if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+  out->block = c->block;
+  out->nontemporal = c->nt ? 1 : 0;
+  out->blocks_per_cu = c->bpc;
+  out->odd_lds = c->odd_lds ? 1 : 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, int32_t trial_steps, lbm_launch* best, float* best_us, lbm_launch* tried,
+                        float* tried_us, int32_t max_tried, int32_t* ntried) {
+  if (!c || !best) return fail(LBM_EINVAL, "NULL argument");
+  if (trial_steps < 2) return fail(LBM_EINVAL, "trial_steps must be >= 2");
+  if (!c->ready) return fail(LBM_ESTATE, "lbm_autotune before lbm_init_fields or lbm_set_populations");
+  if (ntried) *ntried = 0;
+  trial_steps += trial_steps & 1;  // whole even/odd pairs
+  // the trials advance the state; a device copy puts it back after each
+  void* snap = nullptr;
+  if (hipMalloc(&snap, c->F_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LBM_ENOMEM, "snapshot of %zu bytes for autotuning failed", c->F_bytes);
+  }
+  HIP_TRY(hipMemcpyAsync(snap, c->F, c->F_bytes, hipMemcpyDeviceToDevice, c->stream));
+  lbm_launch orig{};
+  (void)lbm_get_launch(c, &orig);
+  const int64_t step0 = c->step;
+  // (threads per block, blocks per CU) of the even step, each with and without
+  // nontemporal access; the odd step keeps its own shape
+  static const int shapes[][2] = {{256, 4}, {256, 2}, {256, 0}, {512, 2}, {512, 0}, {1024, 0}};
+  std::vector<lbm_launch> cands;
+  for (int nt : {1, 0})
+    for (const auto& sh : shapes) {
+      lbm_launch t{};
+      t.block = sh[0];
+      t.nontemporal = nt;
+      t.blocks_per_cu = sh[1];
+      t.odd_lds = 1;
+      cands.push_back(t);
+    }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  lbm_status st = LBM_OK;
+  float best_time = 1e30f;
+  lbm_launch best_t = orig;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    st = fail(LBM_EDEVICE, "event creation failed");
+  for (size_t ci = 0; st == LBM_OK && ci < cands.size(); ++ci) {
+    const lbm_launch& t = cands[ci];
+    st = lbm_set_launch(c, t.block, t.nontemporal, t.blocks_per_cu, t.odd_lds);
+    if (st == LBM_OK) st = lbm_step(c, 2, 0);  // warm-up pair
+    if (st != LBM_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) {
+      st = fail(LBM_EDEVICE, "event record failed");
+      break;
+    }
+    st = lbm_step(c, trial_steps, 0);
+    if (st != LBM_OK) break;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(LBM_EDEVICE, "trial timing failed");
+      break;
+    }
+    const float us = ms * 1000.0f / trial_steps;
+    if (tried && ntried && *ntried < max_tried) {
+      tried[*ntried] = t;
+      if (tried_us) tried_us[*ntried] = us;
+      ++*ntried;
+    }
+    if (us < best_time) {
+      best_time = us;
+      best_t = t;
+    }
+    if (hipMemcpyAsync(c->F, snap, c->F_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+      st = fail(LBM_EDEVICE, "snapshot restore failed");
+      break;
+    }
+    c->step = step0;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  // the state must be back before the snapshot goes, whatever happened above
+  if (hipMemcpyAsync(c->F, snap, c->F_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    if (st == LBM_OK) st = fail(LBM_EDEVICE, "snapshot restore failed");
+  }
+  c->step = step0;
+  (void)hipFree(snap);
+  if (st != LBM_OK) {
+    (void)lbm_set_launch(c, orig.block, orig.nontemporal, orig.blocks_per_cu, orig.odd_lds);
+    return st;
+  }
+  st = lbm_set_launch(c, best_t.block, best_t.nontemporal, best_t.blocks_per_cu, best_t.odd_lds);
+  if (st != LBM_OK) return st;
+  *best = best_t;
+  if (best_us) *best_us = best_time;
   return LBM_OK;
 }
 

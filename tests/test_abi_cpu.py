@@ -1,7 +1,8 @@
 """Host-side checks of the C ABI (no GPU needed).
 
 * the HIP library loads and exports every function the headers in include/ declare
-* the ctypes mirrors of lbm_params / lbm_diag match the C layout (checked with a
+* the ctypes mirrors of lbm_params / lbm_diag / lbm_launch / lbm_batch_tuning match
+  the C layout (checked with a
   small C program compiled by gcc against the header)
 * lbm_state_bytes: 35 padded arrays; 140 B/cell FP32 and 70 B/cell FP16 (Sec. 4:
   the five-field state of a 512^3 grid is about 19 GB)
@@ -43,16 +44,18 @@ def test_struct_layout_matches_header(tmp_path):
     prog = tmp_path / "layout.c"
     prog.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "grlbm.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(lbm_params),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(lbm_params),"
         " offsetof(lbm_params, gamma), offsetof(lbm_params, omega), offsetof(lbm_params, E_ref),"
-        " sizeof(lbm_diag), offsetof(lbm_diag, nonfinite)); return 0;}\n")
+        " sizeof(lbm_diag), offsetof(lbm_diag, nonfinite), sizeof(lbm_launch), offsetof(lbm_launch, odd_lds),"
+        " sizeof(lbm_batch_tuning), offsetof(lbm_batch_tuning, grid)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)], check=True)
     vals = list(map(int, subprocess.run([str(exe)], capture_output=True, text=True,
                                         check=True).stdout.split()))
-    P, D = binding.lbm_params, binding.lbm_diag
+    P, D, L, T = binding.lbm_params, binding.lbm_diag, binding.lbm_launch, binding.lbm_batch_tuning
     assert vals == [ctypes.sizeof(P), P.gamma.offset, P.omega.offset, P.E_ref.offset,
-                    ctypes.sizeof(D), D.nonfinite.offset]
+                    ctypes.sizeof(D), D.nonfinite.offset, ctypes.sizeof(L), L.odd_lds.offset,
+                    ctypes.sizeof(T), T.grid.offset]
 
 
 def test_mms_struct_layout_matches_header(tmp_path):
@@ -138,3 +141,6 @@ def test_null_arguments():
     assert "NULL" in binding.lbm_last_error()
     cnt = ctypes.c_int32(5)
     assert lib.lbm_diagnostics(None, None, 0, ctypes.byref(cnt)) == binding.LBM_EINVAL
+    best = binding.lbm_launch()
+    assert lib.lbm_autotune(None, 10, ctypes.byref(best), None, None, None, 0, None) == binding.LBM_EINVAL
+    assert lib.lbm_get_launch(None, ctypes.byref(best)) == binding.LBM_EINVAL
