@@ -161,9 +161,9 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
  * unit (1..32, enforced by reserving LDS; 0 = no cap; default 4 for FP32 storage and
  * no cap for FP16).  With `odd_lds` = 1 (the default) the odd AA step
  * moves the +-x populations through LDS so that all its HBM accesses are aligned;
- * it runs one block per x-row when nx <= 1024 and otherwise tiles of 512
- * consecutive cells (256 for FP16), and `block` and `blocks_per_cu` then apply to
- * the even step only.
+ * it runs one block per x-row when nx <= 1024 and nx is a multiple of 32 (64 for
+ * FP16), and otherwise tiles of 512 consecutive cells (256 for FP16); `block` and
+ * `blocks_per_cu` then apply to the even step only.
  * Results do not depend on any of these settings.  EINVAL otherwise. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t nontemporal, int32_t blocks_per_cu,
                           int32_t odd_lds);

@@ -44,6 +44,10 @@ constexpr int64_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
 constexpr int kOddTileF32 = 512;           // cells per linear tile of k_step_odd_tiles, FP32
 constexpr int kOddTileF16 = 256;           // the same for FP16 storage
 constexpr int kMaxRowTile = 1024;          // longest x-row k_step_odd_tiles maps to one block
+// rows map to blocks only when nx is a multiple of this (FP32 / FP16): a partly
+// filled last wave costs more than the tile edges
+constexpr int kRowMultipleF32 = 32;
+constexpr int kRowMultipleF16 = 64;
 
 hipError_t launch_step(const StepLaunch& L, hipStream_t s);
 int64_t step_blocks(const Grid& g, int block);

@@ -342,7 +342,7 @@ int64_t step_blocks(const Grid& g, int block) {
 // flight per wave) row blocks and 256-cell tiles at 16.
 OddTiles odd_tiles(const Grid& g, bool f16) {
   OddTiles t;
-  t.rows = g.nx <= kMaxRowTile;
+  t.rows = g.nx <= kMaxRowTile && g.nx % (f16 ? kRowMultipleF16 : kRowMultipleF32) == 0;
   const int tile = f16 ? kOddTileF16 : kOddTileF32;
   t.block = t.rows ? (g.nx + 63) / 64 * 64 : tile;
   t.blocks = t.rows ? (int64_t)g.ny * g.nz : ((int64_t)g.nx * g.ny * g.nz + tile - 1) / tile;

@@ -195,14 +195,18 @@ ODD_LDS_CASES = [
     ("257x3x2 zero-gradient x, FP16 BGK", (257, 3, 2), (1, 0, 0), inputs.BGK, binding.LBM_STORE_F16),
     ("1500x2x2 zero-gradient x, linear tiles", (1500, 2, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
     ("1100x3x1 periodic FP16, linear tiles", (1100, 3, 1), (0, 0, 0), inputs.RLB_SENSOR, binding.LBM_STORE_F16),
+    ("160x3x2 zero-gradient x, one block per row", (160, 3, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
+    ("128x2x3 periodic FP16, one block per row", (128, 2, 3), (0, 0, 0), inputs.RLB_SENSOR, binding.LBM_STORE_F16),
+    ("17x9x5 periodic, many rows per tile", (17, 9, 5), (0, 0, 0), inputs.RLB_SENSOR, None),
 ]
 
 
 @pytest.mark.parametrize("name,dims,bc,coll,storage", ODD_LDS_CASES)
 def test_odd_lds_tiles_bitwise(name, dims, bc, coll, storage):
     """The odd step over tiles of consecutive cells with the +-x populations moved
-    through LDS (one block per row up to nx = 1024, linear 256-cell tiles beyond)
-    ends bitwise where the direct odd step ends, diagnostics included."""
+    through LDS (one block per row when nx <= 1024 is a multiple of 32, 64 for FP16;
+    linear tiles of 512 cells, 256 for FP16, otherwise) ends bitwise where the
+    direct odd step ends, diagnostics included."""
     case = inputs.random_smooth(*dims, seed=sum(dims), amp=0.06, bc=bc, collision=coll)
     say(f"odd step via LDS {name}")
     out = []
