@@ -45,9 +45,28 @@ def cpu_baseline(target_s=15.0):
     dt = time.perf_counter() - t0
     assert np.isfinite(f).all()
     glups = cells * steps / dt / 1e9
-    return {"value": glups, "unit": "GLUP/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    # one thread on the same slab, two steps after one warm-up step
+    oracle.set_num_threads(1)
+    try:
+        f, _ = oracle.run(case.params, f, 1)
+        t0 = time.perf_counter()
+        f, _ = oracle.run(case.params, f, 2)
+        glups_1 = cells * 2 / (time.perf_counter() - t0) / 1e9
+    finally:
+        oracle.set_num_threads(cores)
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": glups, "unit": "GLUP/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, 256x256x32 slab of the 256^3 cTGV initial field, {steps} steps "
-                      f"after 3 warm-up steps, {dt:.1f} s"}
+                      f"after 3 warm-up steps, {dt:.1f} s",
+            "one_thread_value": glups_1, "cpu_model": model}
 
 
 def becker_linf(case, Q):
@@ -441,6 +460,7 @@ def main():
                      "bytes_per_lup": bytes_per_lup, "avg_launch_ms": round(avg_launch_ms, 5)},
         "host_wall_s": round(t_host, 3),
         "copy_bw_gbs": None if bw is None else round(bw, 1),
+        "frac_of_copy_bw": None if bw is None else round(achieved_gbs / bw, 4),
         "diag_records": len(recs),
         "Ek_last": recs[-1]["Ek"] / cells if recs else None,
     }

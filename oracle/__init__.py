@@ -89,6 +89,8 @@ def _load():
     lib.ora_cell_info_size.restype = ctypes.c_int32
     lib.ora_params_size.restype = ctypes.c_int32
     lib.ora_num_threads.restype = ctypes.c_int32
+    lib.ora_set_num_threads.argtypes = [ctypes.c_int32]
+    lib.ora_set_num_threads.restype = None
     if lib.ora_cell_info_size() != ctypes.sizeof(OraCellInfo):
         raise RuntimeError("oracle cell-info layout mismatch")
     if lib.ora_params_size() != ctypes.sizeof(OraParams):
@@ -197,6 +199,11 @@ def run(p: dict, f, nsteps: int, diag_every: int = 0):
 def num_threads() -> int:
     """Threads the oracle's parallel cell loop uses (OpenMP)."""
     return int(_load().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's following steps (results do not depend on it)."""
+    _load().ora_set_num_threads(int(n))
 
 
 def _mms(m: dict) -> OraMms:

@@ -484,6 +484,15 @@ int32_t ora_num_threads(void) {
   return n;
 }
 
+/* Threads for the following parallel regions (n >= 1; a no-op without OpenMP). */
+void ora_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads((int)n);
+#else
+  (void)n;
+#endif
+}
+
 /* Size of the per-cell info record (lets the Python side check its mirror). */
 int32_t ora_cell_info_size(void) { return (int32_t)sizeof(ora_cell_info); }
 int32_t ora_params_size(void) { return (int32_t)sizeof(ora_params); }
