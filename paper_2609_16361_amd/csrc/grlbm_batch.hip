@@ -87,21 +87,18 @@ __global__ void __launch_bounds__(1024) k_batch_step(T* __restrict__ arena, cons
     const Coll c = I->c;
     T* F = arena + I->off;
     // the same arithmetic as a single context uses for this instance, so the
-    // results are bitwise the same
+    // results are bitwise the same.  Every instance takes the zero-gradient form
+    // of the update: on a periodic axis its face flags are false and it reads and
+    // writes exactly what the periodic form does.  A kernel holding both forms
+    // compiled to 113-128 registers (94-99 with one) and ran FP16 batches of
+    // periodic cubes at 21 GLUP/s against 33 with the single form.
     const bool odd = ((t - ts) & 1) != 0;
-    const bool zg = g.zg_x | g.zg_y | g.zg_z;
     const uint32_t skey = step_key(t - ts);  // the instance's own step index
     if (odd) {
       // every lane takes part (barriers inside)
-      if (zg)
-        tile_update_odd<COLL, T, true, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr, skey);
-      else
-        tile_update_odd<COLL, T, false, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr, skey);
+      tile_update_odd<COLL, T, true, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr, skey);
     } else if (act) {
-      if (zg)
-        cell_update<false, COLL, T, true, false, NT>(F, g, c, x, y, z, nullptr, skey);
-      else
-        cell_update<false, COLL, T, false, false, NT>(F, g, c, x, y, z, nullptr, skey);
+      cell_update<false, COLL, T, true, false, NT>(F, g, c, x, y, z, nullptr, skey);
     }
   }
 }
