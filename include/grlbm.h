@@ -241,7 +241,9 @@ typedef struct {
 /* Create a batch: one device arena of arena_bytes for the populations of all its
  * instances, room for max_instances descriptors and max_tiles tiles per group, and
  * time loops captured in graphs of graph_steps steps (1..4096; 1 = no graph).
- * hip_stream as for lbm_create.  EINVAL on bad sizes, ENOMEM if the arena does not
+ * hip_stream as for lbm_create.  The launch shape starts as one 256-cell tile per
+ * block with plain (not nontemporal) access (block 256, nontemporal 0,
+ * blocks_per_cu 0, grid 0).  EINVAL on bad sizes, ENOMEM if the arena does not
  * fit. */
 lbm_status lbm_batch_create(size_t arena_bytes, int32_t max_instances, int32_t max_tiles,
                             int32_t graph_steps, void* hip_stream, lbm_batch** out);
@@ -279,7 +281,10 @@ lbm_status lbm_batch_set_tuning(lbm_batch* b, const lbm_batch_tuning* t);
 
 /* Time every candidate launch shape on the batch's live instances for trial_steps
  * steps each, restoring the populations and the clock after each trial (results do
- * not depend on the shape), and keep the fastest.  best/best_us receive it and its
+ * not depend on the shape), and keep the fastest.  The candidates are blocks of
+ * 128, 256, 512 and 1024 threads, each with and without nontemporal access, as
+ * persistent grids of 8, 16 or 32 resident waves per CU and as one block per tile
+ * (30 shapes).  best/best_us receive it and its
  * time per step; up to max_tried (shape, time) pairs go to tried/tried_us (may be
  * NULL), their number to *ntried.  Needs device memory for one copy of the used
  * arena. */
