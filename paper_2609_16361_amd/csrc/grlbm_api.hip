@@ -46,8 +46,10 @@ lbm_status validate(const lbm_params* p) {
     if (p->bc[a] == LBM_BC_ZERO_GRADIENT && dims[a] < 2)
       return fail(LBM_EINVAL, "zero-gradient axis %d needs >= 2 cells (got %d)", a, dims[a]);
   }
+  // the step kernels index cells in 32 bits, and a tile's end (its first cell plus
+  // up to 1024) must stay representable: grids up to 2^31 - 2^16 cells (1290^3)
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-  if (N > (int64_t)INT32_MAX / 2)
+  if (N > (int64_t)INT32_MAX - 65535)
     return fail(LBM_EINVAL, "grid of %lld cells exceeds the 32-bit cell index range", (long long)N);
 
   if (p->collision != LBM_COLL_RLB_SENSOR && p->collision != LBM_COLL_BGK)

@@ -108,6 +108,13 @@ def test_state_bytes():
     assert binding.lbm_state_bytes(small) == 35 * 4 * per
     small.layout_pad = 1000
     assert binding.lbm_state_bytes(small) == 35 * 4 * ((1300 + 63) // 64 * 64)
+    # one MI355X holds a 1024^3 FP32 state (150 GB of its 288 GB); 32-bit cell
+    # indices allow up to 2^31 - 2^16 cells
+    big = binding.make_params(inputs.tgv(n=8, dims=(8, 8, 8)).params)
+    big.nx = big.ny = big.nz = 1024
+    assert binding.lbm_state_bytes(big) == 35 * 4 * 1024 ** 3
+    big.nx = big.ny = big.nz = 1290
+    assert binding.lbm_state_bytes(big) == 35 * 4 * ((1290 ** 3 + 63) // 64 * 64)
 
 
 @pytest.mark.parametrize("mutate,needle", [
@@ -123,6 +130,7 @@ def test_state_bytes():
     (lambda p: setattr(p, "rho_min", 0.0), "rho_min"),
     (lambda p: setattr(p, "layout_pad", -1), "layout_pad"),
     (lambda p: setattr(p, "T_ref", float("nan")), "T_ref"),
+    (lambda p: (setattr(p, "nx", 1291), setattr(p, "ny", 1291), setattr(p, "nz", 1291)), "32-bit"),
 ])
 def test_validation_rejects(mutate, needle):
     p = binding.make_params(inputs.tgv(n=8, dims=(8, 8, 8)).params)

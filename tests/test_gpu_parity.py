@@ -329,3 +329,52 @@ def test_torch_buffer_and_stream():
         binding.lbm_destroy(ctx)
     Qr, _, _, _ = gpu_run(case, 6)
     assert np.array_equal(Q, Qr)
+
+
+def test_billion_cell_grid_rows_match_small_grid():
+    """A 1024^3 FP32 grid (2^30 cells, a 150 GB state on one device) whose state
+    varies along x only.  The update is local and the neighbours in y and z hold
+    the same values, so after 3 steps every y-z row must equal, bitwise, the row of
+    the same state on a 1024 x 4 x 4 grid; that small run is checked against the
+    oracle.  The fields are built and read back on the device (43 GB of FP64)."""
+    import torch
+    n = 1024
+    small = inputs.random_smooth(n, 4, 4, seed=11)
+    gamma = small.params["gamma"]
+    c0 = 0.08
+    p0 = c0 * c0 / gamma
+    x = np.arange(n)
+    rho = 1.0 + 0.05 * np.sin(2 * math.pi * x / n)
+    ux = 0.5 * c0 * np.sin(4 * math.pi * x / n + 0.3)
+    p = p0 * (1.0 + 0.05 * np.cos(2 * math.pi * x / n))
+    row = inputs.conserved(rho, (ux, 0 * x, 0 * x), p, gamma)            # [5][n]
+    small.Q0 = np.ascontiguousarray(np.broadcast_to(row[:, None, None, :], (5, 4, 4, n)))
+    Qs, _, _, _ = gpu_run(small, 3)
+    for z in range(4):
+        for y in range(4):
+            assert np.array_equal(Qs[:, z, y, :], Qs[:, 0, 0, :])
+    fo, _ = oracle.run(small.params, oracle.init(small.params, small.Q0), 3)
+    Qo = oracle.moments(small.params, fo)
+    for k in range(5):
+        scale = max(np.abs(Qo[k]).max(), 1e-3)
+        assert np.abs(Qs[k] - Qo[k]).max() <= 1e-5 * scale, k
+
+    big = dict(small.params, ny=n, nz=n)
+    nbytes = binding.lbm_state_bytes(binding.make_params(big))
+    free, _ = torch.cuda.mem_get_info()
+    if free < nbytes + 5 * 8 * n ** 3 + (4 << 30):
+        pytest.skip(f"needs {(nbytes + 5 * 8 * n ** 3) / 1e9:.0f} GB of free device memory")
+    say("1024^3: device fields, init, 3 steps, readout")
+    stream = torch.cuda.current_stream()
+    Qd = torch.empty((5, n, n, n), dtype=torch.float64, device="cuda")
+    Qd.copy_(torch.from_numpy(row).cuda()[:, None, None, :].expand(5, n, n, n))
+    with binding.Solver(big, stream=stream.cuda_stream) as s:
+        binding.lbm_init_fields_device(s.ctx, Qd.data_ptr())
+        s.step(3)
+        binding.lbm_moments_device(s.ctx, Qd.data_ptr())      # the fields buffer is reused
+        torch.cuda.synchronize()
+    ref = torch.from_numpy(np.ascontiguousarray(Qs[:, 0, 0, :])).cuda()
+    same = bool(torch.equal(Qd, ref[:, None, None, :].expand(5, n, n, n)))
+    del Qd
+    torch.cuda.empty_cache()
+    assert same
