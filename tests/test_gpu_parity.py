@@ -183,6 +183,22 @@ def test_launch_shapes_bitwise(block, nt, bpc):
     assert np.array_equal(fr, fb)
 
 
+def test_block_mapping_both_branches_bitwise():
+    """The even and direct odd steps take a row segment per block when whole blocks
+    fit a row (blocks of 64, 256, 1024 on 1024-cell rows) and consecutive cells
+    across rows otherwise (320, 448): both mappings give the same bits."""
+    case = inputs.random_smooth(1024, 2, 3, seed=12, amp=0.05, bc=(1, 0, 0))
+    out = []
+    for block in (64, 256, 1024, 320, 448):
+        say(f"block mapping, block={block}")
+        with binding.Solver(case.params, block=block, odd_lds=0) as s:
+            s.init(case.Q0)
+            s.step(5, 2)
+            out.append(s.populations()[0])
+    for f in out[1:]:
+        assert np.array_equal(out[0], f)
+
+
 ODD_LDS_CASES = [
     ("300x3x2 zero-gradient x, tiles span rows", (300, 3, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
     ("100x5x3 periodic, wraps in and out of tiles", (100, 5, 3), (0, 0, 0), inputs.RLB_SENSOR, None),
