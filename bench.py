@@ -257,14 +257,16 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
                 max_active_cells=8 * 2 ** 20):
     """Serving mix (Poisson arrivals at `rate`, 40% Sod variants, 40% Taylor-Green,
     20% Becker; 1000-20000 steps; FP32 or FP16 storage per request) through the
-    continuous-batching server under an HBM budget, against the same requests
-    served one at a time in plain FP32 single contexts."""
+    continuous-batching server under an HBM budget (its default admission order),
+    against the same requests served one at a time, in arrival order, in plain FP32
+    single contexts."""
     import numpy as np
     import torch
     from paper_2609_16361_amd import binding, inputs, serve
     trace = inputs.serving_trace(count=count, rate=rate, seed=seed)
     work = sum(r.case.cells * r.steps for r in trace)
     out = {"requests": count, "rate_per_s": rate, "seed": seed, "budget_bytes": budget_bytes,
+           "admission": "largest work first among arrived requests, any request waiting over 2 s first",
            "offered_glup": work / 1e9,
            "mix": {k: sum(1 for r in trace if r.kind == k) for k in ("sod", "tgv", "becker")},
            "fp16_share": sum(r.storage for r in trace) / count}

@@ -1,14 +1,19 @@
 """Continuous-batching solve server over one lbm_batch.
 
 Requests (an initial state, a step count, a storage type) arrive over time.  The
-serving loop admits every request that has arrived, in arrival order, as long as
-its populations fit in the HBM budget (the batch arena) and the active-cell cap
+serving loop admits requests that have arrived (in the order below) as long as
+their populations fit in the HBM budget (the batch arena) and the active-cell cap
 allows; it then advances the whole batch by one graph-captured chunk of steps
 (every admitted instance overlaps with the others on the device), retires the
 instances that have made their steps, reads their conserved fields back and frees
 their memory for the next arrivals.  A result is exactly what the same request
 gives alone: the batch updates each instance with the same arithmetic as a single
 context, and an instance freezes when it reaches its own step count.
+
+Admission order is largest work (cells x steps) first among the arrived requests,
+except that a request waiting longer than max_wait_s (2 s by default) goes first
+in arrival order; this starts the long solves early and fills the gaps with short
+ones.  order="fifo" admits strictly in arrival order.
 
 The loop runs on the wall clock (arrival times are seconds after start); latency
 is completion minus arrival.  A stand-in backend with the same methods as
@@ -85,7 +90,8 @@ class Server:
 
     def __init__(self, backend, arena_bytes: int, max_active_cells: int | None = None,
                  chunk_steps: int = 50, result_handler=None, clock=time.perf_counter,
-                 sync=None, max_instances: int = 4096, storage_override: int | None = None):
+                 sync=None, max_instances: int = 4096, storage_override: int | None = None,
+                 order: str = "largest", max_wait_s: float | None = 2.0):
         self.b = backend
         self.arena_bytes = int(arena_bytes)
         self.max_cells = max_active_cells
@@ -96,6 +102,15 @@ class Server:
         self.max_instances = max_instances
         # None: each request's own storage; else every request in this storage
         self.storage_override = storage_override
+        # "fifo": admit arrived requests in arrival order, the first that does not
+        # fit blocks the rest; "largest": among the arrived requests, largest work
+        # (cells x steps) first, skipping those that do not fit yet, except that
+        # requests waiting longer than max_wait_s go first in arrival order (so a
+        # stream of large requests cannot hold a small one back without bound)
+        if order not in ("fifo", "largest"):
+            raise ValueError(f"order must be 'fifo' or 'largest', not {order!r}")
+        self.order = order
+        self.max_wait = max_wait_s
 
     def serve(self, requests) -> ServeStats:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -109,27 +124,34 @@ class Server:
         t0 = self.clock()
         while pending or active:
             now = self.clock() - t0
-            # admission: arrived requests in order while memory and the cell cap allow
-            while pending and pending[0].arrival <= now:
-                r = pending[0]
+            # admission: arrived requests while memory and the cell cap allow
+            arrived = [r for r in pending if r.arrival <= now]
+            if self.order == "largest":
+                overdue = [r for r in arrived if self.max_wait is not None and now - r.arrival > self.max_wait]
+                rest = sorted((r for r in arrived if r not in overdue), key=lambda r: -r.case.cells * r.steps)
+                arrived = overdue + rest
+            for r in arrived:
                 nb = state_bytes(r.case.params, stg[r.rid])
                 if nb > self.arena_bytes:
                     out[r.rid].ok = False        # can never fit: rejected
                     out[r.rid].completed = now
-                    pending.pop(0)
+                    pending.remove(r)
                     continue
-                if used_bytes + nb > self.arena_bytes or len(active) >= self.max_instances:
-                    break
-                if self.max_cells is not None and active and used_cells + r.case.cells > self.max_cells:
-                    break
-                try:
-                    iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=stg[r.rid])
-                except RuntimeError as e:
-                    # no free run of that size yet (fragmentation): wait for retirements
-                    if getattr(e, "status", None) == ENOMEM and active:
+                fits = used_bytes + nb <= self.arena_bytes and len(active) < self.max_instances and not (
+                    self.max_cells is not None and active and used_cells + r.case.cells > self.max_cells)
+                if fits:
+                    try:
+                        iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=stg[r.rid])
+                    except RuntimeError as e:
+                        # no free run of that size yet (fragmentation): wait for retirements
+                        if getattr(e, "status", None) != ENOMEM or not active:
+                            raise
+                        fits = False
+                if not fits:
+                    if self.order == "fifo":
                         break
-                    raise
-                pending.pop(0)
+                    continue
+                pending.remove(r)
                 active[iid] = (r, nb)
                 used_bytes += nb
                 used_cells += r.case.cells

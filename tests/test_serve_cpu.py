@@ -1,5 +1,6 @@
 """Serving loop logic on the CPU with a stand-in backend (no GPU): admission in
-arrival order under the HBM budget and the active-cell cap, overlap of requests,
+arrival order (or largest work first, with a wait bound) under the HBM budget and
+the active-cell cap, overlap of requests,
 retirement at each request's own step count, latency bookkeeping, rejection of a
 request that can never fit, and the served trace generator."""
 import numpy as np
@@ -21,13 +22,14 @@ class FakeBatch:
 
     def __init__(self, clock, dt=1e-3):
         self.clock, self.dt = clock, dt
-        self.inst, self.next_id, self.log = {}, 0, []
+        self.inst, self.next_id, self.log, self.added_steps = {}, 0, [], []
 
     def add(self, params, Q, steps, storage=0):
         i = self.next_id
         self.next_id += 1
         self.inst[i] = [0, steps, Q]
         self.log.append(("add", i, self.clock.t))
+        self.added_steps.append(steps)
         return i
 
     def run(self, n):
@@ -58,7 +60,7 @@ def test_fifo_budget_and_overlap():
     fb = FakeBatch(clk)
     reqs = [make_req(i, 0.01 * i, 1600, 100 + 50 * i) for i in range(6)]
     one = serve.state_bytes(reqs[0].case.params, 0)
-    srv = serve.Server(fb, arena_bytes=3 * one, chunk_steps=10, clock=clk)
+    srv = serve.Server(fb, arena_bytes=3 * one, chunk_steps=10, clock=clk, order="fifo")
     st = srv.serve(reqs)
     s = st.summary()
     assert s["completed"] == 6 and s["failed"] == 0
@@ -94,10 +96,43 @@ def test_cell_cap_and_rejection():
     fb = FakeBatch(clk)
     reqs = [make_req(0, 0.0, 1600, 40), make_req(1, 0.0, 1600, 40), make_req(2, 0.0, 16000, 10)]
     one = serve.state_bytes(reqs[0].case.params, 0)
-    srv = serve.Server(fb, arena_bytes=4 * one, max_active_cells=2000, chunk_steps=8, clock=clk)
+    srv = serve.Server(fb, arena_bytes=4 * one, max_active_cells=2000, chunk_steps=8, clock=clk, order="fifo")
     st = srv.serve(reqs)
     assert st.max_active == 1                     # the cell cap admits one at a time
     assert [o.ok for o in st.outcomes] == [True, True, False]   # the big one never fits
+
+
+def test_largest_work_first_skips_what_does_not_fit():
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    # work (cells x steps): C 320k, B 160k, A 80k, D 3.2k; all arrived at t = 0
+    A, B, C, D = (make_req(0, 0.0, 1600, 50), make_req(1, 0.0, 320, 500), make_req(2, 0.0, 3200, 100),
+                  make_req(3, 0.0, 320, 10))
+    nb = {r.rid: serve.state_bytes(r.case.params, 0) for r in (A, B, C, D)}
+    srv = serve.Server(fb, arena_bytes=nb[2] + nb[1] + nb[3], chunk_steps=10, clock=clk, order="largest")
+    st = srv.serve([A, B, C, D])
+    # C, B, then D fits where A does not; A once C retires (requests told apart by steps)
+    assert fb.added_steps == [100, 500, 10, 50]
+    assert st.summary()["completed"] == 4
+
+
+def test_largest_work_first_with_a_wait_bound():
+    def order_of(max_wait):
+        clk = FakeClock()
+        fb = FakeBatch(clk)
+        # one at a time by the cell cap; the first runs 0.2 s, during which the small
+        # request (arrived first) and the large one (arrived next) wait
+        reqs = [make_req(0, 0.0, 1600, 200), make_req(1, 0.0, 1600, 5), make_req(2, 0.001, 1600, 150)]
+        serve.Server(fb, arena_bytes=1 << 30, max_active_cells=2000, chunk_steps=10, clock=clk,
+                     order="largest", max_wait_s=max_wait).serve(reqs)
+        return fb.added_steps
+    assert order_of(None) == [200, 150, 5]     # largest work first
+    assert order_of(0.05) == [200, 5, 150]     # both overdue: arrival order
+
+
+def test_unknown_order_rejected():
+    with pytest.raises(ValueError):
+        serve.Server(FakeBatch(FakeClock()), arena_bytes=1, order="random")
 
 
 def test_sequential_baseline_fifo():
