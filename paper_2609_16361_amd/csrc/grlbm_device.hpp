@@ -474,6 +474,107 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
   }
 }
 
+// The even AA step for FP16 storage with two consecutive cells per lane.  The
+// even step only touches the cell's own slots, so cells n and n + 1 (n even)
+// share every access: each of the 35 slots moves as one 4-byte pair (low half
+// cell n, high half cell n + 1), and a wave moves 256 bytes per array instead of
+// 128.  The two cells are collided one after the other with the same call and
+// rounded with the same per-cell dither as st_pop, so the stored bits are those
+// of cell_update<false, COLL, _Float16, ...>.  Both cells must exist.
+template <bool NT>
+__device__ __forceinline__ uint32_t ld_pair(const _Float16* p) {
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+  if constexpr (NT) return __builtin_nontemporal_load(q);
+  return *q;
+}
+template <bool NT>
+__device__ __forceinline__ void st_pair(_Float16* p, uint32_t v) {
+  uint32_t* q = reinterpret_cast<uint32_t*>(p);
+  if constexpr (NT) {
+    __builtin_nontemporal_store(v, q);
+  } else {
+    *q = v;
+  }
+}
+__device__ __forceinline__ float half_lo(uint32_t w) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)));
+}
+__device__ __forceinline__ float half_hi(uint32_t w) {
+  return static_cast<float>(__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)));
+}
+// The FP16 bits st_pop<_Float16> stores for v.
+__device__ __forceinline__ uint32_t half_bits(float v, uint32_t hc, int slot) {
+  const uint32_t mul = 0x9e3779b9u + 2u * (uint32_t)slot * 0x6c8e9cf5u;
+  const uint32_t dither = (hc * mul) >> 19;
+  v = __uint_as_float((__float_as_uint(v) + dither) & 0xffffe000u);
+  asm volatile("" : "+v"(v));
+  return (uint32_t)__builtin_bit_cast(uint16_t, static_cast<_Float16>(v));
+}
+
+template <int COLL, bool ZG, bool DIAG, bool NT>
+__device__ __forceinline__ void pair_update_even(_Float16* __restrict__ F, const Grid& g, const Coll& c, int n,
+                                                 float* vals, uint32_t skey) {
+  const int64_t S = g.S;
+  uint32_t w[kPop];  // slot pairs: inputs, overwritten half by half with the outputs
+#pragma unroll
+  for (int s = 0; s < kPop; ++s) w[s] = ld_pair<NT>(F + (int64_t)s * S + n);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    // one cell at a time: the second cell's inputs stay packed until its turn
+    // (otherwise they are unpacked early, next to the first cell's, and the
+    // registers double)
+    if (h == 1) {
+#pragma unroll
+      for (int s = 0; s < kPop; ++s) asm volatile("" : "+v"(w[s]));
+    }
+    const int cell = n + h;
+    bool lo_x = false, hi_x = false, lo_y = false, hi_y = false, lo_z = false, hi_z = false;
+    if constexpr (ZG) {
+      const int row = cell / g.nx;
+      const int x = cell - row * g.nx;
+      const int z = row / g.ny;
+      const int y = row - z * g.ny;
+      lo_x = g.zg_x && x == 0;
+      hi_x = g.zg_x && x == g.nx - 1;
+      lo_y = g.zg_y && y == 0;
+      hi_y = g.zg_y && y == g.ny - 1;
+      lo_z = g.zg_z && z == 0;
+      hi_z = g.zg_z && z == g.nz - 1;
+    }
+    float f[kPop];
+#pragma unroll
+    for (int s = 0; s < kPop; ++s) f[s] = h ? half_hi(w[s]) : half_lo(w[s]);
+    CellDiag d;
+    collide<COLL, DIAG, true>(f, c, &d);
+    if constexpr (DIAG) {
+      vals[0] += d.ek;
+      vals[1] += d.eps_s;
+      vals[2] += d.eps_d;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) vals[3 + k] += d.dq[k];
+      vals[8] += d.nonfinite;
+    }
+    const uint32_t hn = cell_key(cell, skey);
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      const float* fo = f + 7 * k;
+      const int s0 = 7 * k;
+      // own cell, opposite slot; the ghost copy on a zero-gradient face
+      const float v[kQ] = {fo[0],
+                           (ZG && lo_x) ? fo[1] : fo[2], (ZG && hi_x) ? fo[2] : fo[1],
+                           (ZG && lo_y) ? fo[3] : fo[4], (ZG && hi_y) ? fo[4] : fo[3],
+                           (ZG && lo_z) ? fo[5] : fo[6], (ZG && hi_z) ? fo[6] : fo[5]};
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) {
+        const uint32_t bits = half_bits(v[i], hn, s0 + i);
+        w[s0 + i] = h ? (w[s0 + i] & 0xffffu) | (bits << 16) : (w[s0 + i] & 0xffff0000u) | bits;
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kPop; ++s) st_pair<NT>(F + (int64_t)s * S + n, w[s]);
+}
+
 // ----------------------------------------------------- odd update of one tile
 // The odd half step of a tile of B = blockDim.x consecutive cells [n0, n0 + B) of
 // one grid (the tile may start mid-row and span rows), with the +-x populations

@@ -44,6 +44,7 @@ constexpr int64_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
 constexpr int kOddTileF32 = 512;           // cells per linear tile of k_step_odd_tiles, FP32
 constexpr int kOddTileF16 = 256;           // the same for FP16 storage
 constexpr int kMaxRowTile = 1024;          // longest x-row k_step_odd_tiles maps to one block
+constexpr int64_t kPairMinCells = 1 << 23;  // FP16 even steps take two cells per lane from here on
 // rows map to blocks only when nx is a multiple of this (FP32 / FP16): a partly
 // filled last wave costs more than the tile edges
 constexpr int kRowMultipleF32 = 32;
@@ -59,6 +60,8 @@ struct OddTiles {
 };
 OddTiles odd_tiles(const Grid& g, bool f16);  // launch shape of k_step_odd_tiles
 int64_t launch_blocks(const StepLaunch& L);  // blocks (= diagnostic partials) of a launch
+bool even_pairs(const StepLaunch& L);        // the even step runs k_step_even_pairs
+int64_t pair_blocks(const StepLaunch& L);    // its blocks
 hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s);
 hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const double* Q, int64_t N,
                        hipStream_t s);

@@ -122,3 +122,25 @@ def test_precision_workload_against_oracle():
             e = np.linalg.norm(Q[k] - Qo[k]) / np.linalg.norm(Qo[k])
             say(f"   {name} field {k} vs oracle {e:.2e}")
             assert e <= bars[name][1], (name, k, e)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1)])
+def test_even_step_cell_pairs_bitwise(bc):
+    """From 2^23 cells on, FP16 even steps with blocks of up to 256 threads take two
+    consecutive cells per lane (4-byte accesses); 512-thread blocks take one.  Both
+    give the same bits, diagnostics to FP32 summation order."""
+    case = inputs.random_smooth(256, 256, 128, seed=21, amp=0.05, bc=bc)
+    out = []
+    for block in (256, 512):
+        say(f"FP16 256x256x128 bc={bc} block={block}")
+        with binding.Solver(case.params, storage=binding.LBM_STORE_F16, block=block) as s:
+            s.init(case.Q0)
+            s.step(4, 2)
+            f, st = s.populations()
+            recs, status = s.diagnostics()
+        out.append((f, recs, status))
+    (fa, ra, sa), (fb, rb, sb) = out
+    assert sa == sb == binding.LBM_OK
+    assert np.array_equal(fa, fb)
+    for a, b in zip(ra, rb):
+        assert a["Ek"] == pytest.approx(b["Ek"], rel=1e-5)
