@@ -353,6 +353,8 @@ def main():
                     help="only the manufactured-solution convergence study (64^3-256^3)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving mix")
     ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=50.0,
+                    help="mean Poisson arrival rate of the serving mix, requests per second")
     ap.add_argument("--copy-only", type=int, default=0, metavar="BYTES",
                     help="only run the streaming-copy probe on BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -387,7 +389,7 @@ def main():
         print(json.dumps({"mms": bench_mms(stream)}), flush=True)
         return
     if args.serve_only:
-        print(json.dumps({"serve": bench_serve(stream, count=args.serve_requests)}), flush=True)
+        print(json.dumps({"serve": bench_serve(stream, count=args.serve_requests, rate=args.serve_rate)}), flush=True)
         return
 
     case = inputs.tgv(n=args.n, diag_every=args.diag_every)
@@ -469,7 +471,7 @@ def main():
     if not args.no_batch:
         out["batch"] = bench_batch(stream=stream)
     if not args.no_serve:
-        out["serve"] = bench_serve(stream, count=args.serve_requests)
+        out["serve"] = bench_serve(stream, count=args.serve_requests, rate=args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
