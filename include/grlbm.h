@@ -163,7 +163,10 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
  * moves the +-x populations through LDS so that all its HBM accesses are aligned;
  * it runs one block per x-row when nx <= 1024 and nx is a multiple of 32 (64 for
  * FP16), and otherwise tiles of 512 consecutive cells (256 for FP16); `block` and
- * `blocks_per_cu` then apply to the even step only.
+ * `blocks_per_cu` then apply to the even step only.  With FP16 storage on grids of
+ * 2^23 cells and more, a lane takes two consecutive cells (4-byte accesses) in the
+ * even step when `block` <= 256 and the cell count is even, and in the LDS odd step
+ * when nx is 384 or 512.
  * Results do not depend on any of these settings.  EINVAL otherwise. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t block, int32_t nontemporal, int32_t blocks_per_cu,
                           int32_t odd_lds);

@@ -726,4 +726,135 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
   }
 }
 
+// ------------------------------------- FP16 odd update of one row, two cells a lane
+// The odd half step of one x-row (y, z) with FP16 storage and two consecutive cells
+// per lane: lane l (0 <= l < nx / 2) holds cells x = 2l and 2l + 1 (nx even).  The +-x populations move through LDS as in tile_update_odd
+// (xs holds 15 nx floats: slot 1, slot 2, sink).  The rest, y and z populations of
+// the two cells sit at consecutive elements of one array, 4-byte aligned because
+// every row starts at an even cell, and both cells share the row and therefore the
+// neighbour rows and the y and z zero-gradient flags: each of those accesses moves
+// one half pair, as in pair_update_even.  On each of the y and z axes a cell stores
+// exactly two populations, to the neighbour rows or, on a zero-gradient face, one of
+// them to its own cell (the ghost copy); the pair words are named for those two
+// stores.  The cells are collided one after the other with the same call, and every
+// value is rounded with the dither of its destination cell and slot, so the bits
+// are those of tile_update_odd<COLL, _Float16, ...>.  The block is the row's nx / 2
+// lanes, and every one must call this (two barriers).
+template <int COLL, bool ZG, bool DIAG, bool NT>
+__device__ __forceinline__ void pair_row_update_odd(_Float16* __restrict__ F, const Grid& g, const Coll& c,
+                                                    int lane, int y, int z, float* xs, float* vals,
+                                                    uint32_t skey) {
+  const int nx = g.nx;
+  const int x0 = 2 * lane;
+  const Nbr b = make_nbr(g, x0, y, z);  // of the first cell; the second is b.n + 1
+  const int64_t S = g.S;
+  float* s1 = xs;              // slot 1 of the row's cells, [field][nx]
+  float* s2 = xs + 5 * nx;     // slot 2
+  float* sink = xs + 10 * nx;  // [field][nx], written and never read
+  // w[7k]: slot 0; w[7k + 3], w[7k + 4]: the two y stores (below); w[7k + 5],
+  // w[7k + 6]: the two z stores.  Inputs first, then overwritten half by half.
+  uint32_t w[kPop];
+#pragma unroll
+  for (int k = 0; k < kFields; ++k) {
+    const _Float16* Fk = F + (int64_t)(7 * k) * S;
+    const uint32_t p1 = ld_pair<NT>(Fk + 1 * S + b.n);
+    const uint32_t p2 = ld_pair<NT>(Fk + 2 * S + b.n);
+    s1[k * nx + x0] = half_lo(p1);
+    s1[k * nx + x0 + 1] = half_hi(p1);
+    s2[k * nx + x0] = half_lo(p2);
+    s2[k * nx + x0 + 1] = half_hi(p2);
+    w[7 * k] = ld_pair<NT>(Fk + b.n);
+#pragma unroll
+    for (int i = 3; i < kQ; ++i) w[7 * k + i] = ld_pair<NT>(Fk + odd_src<ZG>(g, b, i));
+  }
+  __syncthreads();
+  // where the two stores of each axis go: (slot, cell) of the first and the second
+  const bool ylo = ZG && b.lo_y, yhi = ZG && b.hi_y, zlo = ZG && b.lo_z, zhi = ZG && b.hi_z;
+  const int64_t dst[4] = {yhi ? 4 * S + b.n : 3 * S + b.yp, ylo ? 3 * S + b.n : 4 * S + b.ym,
+                          zhi ? 6 * S + b.n : 5 * S + b.zp, zlo ? 5 * S + b.n : 6 * S + b.zm};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h == 1) {
+#pragma unroll
+      for (int s = 0; s < kPop; ++s) asm volatile("" : "+v"(w[s]));
+    }
+    const int x = x0 + h;
+    const bool lo = ZG && g.zg_x && x == 0;
+    const bool hi = ZG && g.zg_x && x == nx - 1;
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    // f_{+x}: slot 1 of the cell itself (zero-gradient face) or slot 2 of the left
+    // neighbour; f_{-x}: slot 2 of the cell itself or slot 1 of the right neighbour
+    const float* r1 = lo ? s1 + x : s2 + xm;
+    const float* r2 = hi ? s2 + x : s1 + xp;
+    float* w1 = hi ? sink + x : s1 + xp;
+    float* w1g = lo ? s1 + x : sink + x;
+    float* w2 = lo ? sink + x : s2 + xm;
+    float* w2g = hi ? s2 + x : sink + x;
+    float f[kPop];
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      f[7 * k] = h ? half_hi(w[7 * k]) : half_lo(w[7 * k]);
+      f[7 * k + 1] = r1[k * nx];
+      f[7 * k + 2] = r2[k * nx];
+#pragma unroll
+      for (int i = 3; i < kQ; ++i) f[7 * k + i] = h ? half_hi(w[7 * k + i]) : half_lo(w[7 * k + i]);
+    }
+    CellDiag d;
+    collide<COLL, DIAG, true>(f, c, &d);
+    if constexpr (DIAG) {
+      vals[0] += d.ek;
+      vals[1] += d.eps_s;
+      vals[2] += d.eps_d;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) vals[3 + k] += d.dq[k];
+      vals[8] += d.nonfinite;
+    }
+    const int n = b.n + h;
+    const uint32_t hn = cell_key(n, skey);
+    const uint32_t hy0 = yhi ? hn : cell_key(b.yp + h, skey);
+    const uint32_t hy1 = ylo ? hn : cell_key(b.ym + h, skey);
+    const uint32_t hz0 = zhi ? hn : cell_key(b.zp + h, skey);
+    const uint32_t hz1 = zlo ? hn : cell_key(b.zm + h, skey);
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      const float* fo = f + 7 * k;
+      const int s0 = 7 * k;
+      const uint32_t bits[5] = {half_bits(fo[0], hn, s0),
+                                yhi ? half_bits(fo[4], hy0, s0 + 4) : half_bits(fo[3], hy0, s0 + 3),
+                                ylo ? half_bits(fo[3], hy1, s0 + 3) : half_bits(fo[4], hy1, s0 + 4),
+                                zhi ? half_bits(fo[6], hz0, s0 + 6) : half_bits(fo[5], hz0, s0 + 5),
+                                zlo ? half_bits(fo[5], hz1, s0 + 5) : half_bits(fo[6], hz1, s0 + 6)};
+      const int ws[5] = {s0, s0 + 3, s0 + 4, s0 + 5, s0 + 6};
+#pragma unroll
+      for (int j = 0; j < 5; ++j)
+        w[ws[j]] = h ? (w[ws[j]] & 0xffffu) | (bits[j] << 16) : (w[ws[j]] & 0xffff0000u) | bits[j];
+      w1[k * nx] = fo[1];
+      w2[k * nx] = fo[2];
+      if constexpr (ZG) {
+        w1g[k * nx] = fo[1];
+        w2g[k * nx] = fo[2];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kFields; ++k) {
+    _Float16* Fk = F + (int64_t)(7 * k) * S;
+    st_pair<NT>(Fk + b.n, w[7 * k]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) st_pair<NT>(Fk + dst[j], w[7 * k + 3 + j]);
+  }
+  __syncthreads();
+  // write back both cells' x slots, rounded with their own keys
+  const uint32_t ha = cell_key(b.n, skey), hb = cell_key(b.n + 1, skey);
+#pragma unroll
+  for (int k = 0; k < kFields; ++k) {
+    _Float16* Fk = F + (int64_t)(7 * k) * S;
+    st_pair<NT>(Fk + 1 * S + b.n, half_bits(s1[k * nx + x0], ha, 7 * k + 1) |
+                                      (half_bits(s1[k * nx + x0 + 1], hb, 7 * k + 1) << 16));
+    st_pair<NT>(Fk + 2 * S + b.n, half_bits(s2[k * nx + x0], ha, 7 * k + 2) |
+                                      (half_bits(s2[k * nx + x0 + 1], hb, 7 * k + 2) << 16));
+  }
+}
+
 }  // namespace grlbm

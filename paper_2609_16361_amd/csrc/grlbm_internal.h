@@ -49,6 +49,12 @@ constexpr int64_t kPairMinCells = 1 << 23;  // FP16 even steps take two cells pe
 // filled last wave costs more than the tile edges
 constexpr int kRowMultipleF32 = 32;
 constexpr int kRowMultipleF16 = 64;
+// FP16 odd steps take two cells per lane, one row per block, on grids of
+// kPairMinCells and more whose nx is a multiple of kRowMultipleOddPairs (whole
+// waves of pairs) from kMinRowPairs to kMaxRowPairs
+constexpr int kRowMultipleOddPairs = 128;
+constexpr int kMinRowPairs = 384;
+constexpr int kMaxRowPairs = 512;
 
 hipError_t launch_step(const StepLaunch& L, hipStream_t s);
 int64_t step_blocks(const Grid& g, int block);
@@ -62,6 +68,8 @@ OddTiles odd_tiles(const Grid& g, bool f16);  // launch shape of k_step_odd_tile
 int64_t launch_blocks(const StepLaunch& L);  // blocks (= diagnostic partials) of a launch
 bool even_pairs(const StepLaunch& L);        // the even step runs k_step_even_pairs
 int64_t pair_blocks(const StepLaunch& L);    // its blocks
+bool odd_pairs(const StepLaunch& L);         // the odd step runs k_step_odd_row_pairs
+int odd_pair_lds(const Grid& g);             // its dynamic LDS bytes per block
 hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s);
 hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const double* Q, int64_t N,
                        hipStream_t s);

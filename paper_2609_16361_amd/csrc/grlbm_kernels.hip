@@ -155,6 +155,25 @@ __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
+// Odd AA step for FP16 storage with two consecutive cells per lane, one x-row per
+// block (pair_row_update_odd, blockDim.x = nx / 2 <= 256); the rows for which
+// odd_pairs holds.  Bitwise the same result as k_step_odd_tiles.
+template <int COLL, bool ZG, bool DIAG, bool NT>
+__global__ void __launch_bounds__(256) k_step_odd_row_pairs(_Float16* __restrict__ F, Grid g, Coll c,
+                                                             float* __restrict__ partials, uint32_t skey) {
+  extern __shared__ float xs[];
+  const int row = (int)blockIdx.x;
+  const int z = row / g.ny;
+  const int y = row - z * g.ny;
+  float vals[kDiagVals];
+  if constexpr (DIAG) {
+#pragma unroll
+    for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
+  }
+  pair_row_update_odd<COLL, ZG, DIAG, NT>(F, g, c, (int)threadIdx.x, y, z, xs, vals, skey);
+  if constexpr (DIAG) block_reduce_store(vals, partials);
+}
+
 // One block of 1024 threads per value j: partials[nblocks][9] -> rec[j].  Each
 // thread sums a fixed strided subset with compensated (Kahan) summation, then a
 // fixed-order tree in LDS; the result does not depend on timing.
@@ -310,6 +329,13 @@ template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC>
 static hipError_t launch_step_nt(const StepLaunch& L, hipStream_t s) {
   const Grid& g = L.g;
   T* F = (T*)L.F;
+  if constexpr (ODD && sizeof(T) == 2 && !SRC) {
+    if (odd_pairs(L)) {
+      hipLaunchKernelGGL((k_step_odd_row_pairs<COLL, ZG, DIAG, NT>), dim3((unsigned)((int64_t)g.ny * g.nz)),
+                         dim3(g.nx / 2), odd_pair_lds(g), s, F, g, L.c, L.partials, L.skey);
+      return hipGetLastError();
+    }
+  }
   if (ODD && L.odd_lds) {
     const OddTiles ot = odd_tiles(g, L.f16);
     if (ot.rows)
@@ -402,12 +428,25 @@ bool even_pairs(const StepLaunch& L) {
   return !L.odd && L.f16 && !L.src && L.block <= 256 && N % 2 == 0 && N >= kPairMinCells;
 }
 
+bool odd_pairs(const StepLaunch& L) {
+  // measured against k_step_odd_tiles: +6-9% at 384^3 and +5% at 512^3; -3% at 256^3
+  // (one 128-lane block per row; two rows per block did worse), and nothing at 768^3
+  // or 1024^3 (512-lane blocks)
+  const int64_t N = (int64_t)L.g.nx * L.g.ny * L.g.nz;
+  const int nx = L.g.nx;
+  return L.odd && L.odd_lds && L.f16 && !L.src && nx % kRowMultipleOddPairs == 0 && nx >= kMinRowPairs &&
+         nx <= kMaxRowPairs && N >= kPairMinCells;
+}
+
+int odd_pair_lds(const Grid& g) { return 15 * (int)sizeof(float) * g.nx; }
+
 int64_t pair_blocks(const StepLaunch& L) {
   const int64_t pairs = (int64_t)L.g.nx * L.g.ny * L.g.nz / 2;
   return (pairs + L.block - 1) / L.block;
 }
 
 int64_t launch_blocks(const StepLaunch& L) {
+  if (odd_pairs(L)) return (int64_t)L.g.ny * L.g.nz;
   if (L.odd && L.odd_lds) return odd_tiles(L.g, L.f16).blocks;
   return even_pairs(L) ? pair_blocks(L) : step_blocks(L.g, L.block);
 }

@@ -144,3 +144,30 @@ def test_even_step_cell_pairs_bitwise(bc):
     assert np.array_equal(fa, fb)
     for a, b in zip(ra, rb):
         assert a["Ek"] == pytest.approx(b["Ek"], rel=1e-5)
+
+
+@pytest.mark.parametrize("dims,bc,coll", [((384, 192, 128), (0, 1, 1), inputs.RLB_SENSOR),
+                                          ((512, 128, 128), (1, 1, 0), inputs.BGK),
+                                          ((512, 256, 64), (1, 0, 1), inputs.RLB_SENSOR),
+                                          ((1024, 64, 128), (1, 0, 1), inputs.RLB_SENSOR)])
+def test_odd_step_row_pairs_bitwise(dims, bc, coll):
+    """From 2^23 cells on, FP16 odd steps on rows of 384 or 512 cells take two
+    consecutive cells per lane, one row per block; the direct odd step (one cell per
+    lane, no LDS) gives the same bits, diagnostics to FP32 summation order.  (The
+    1024-cell rows take the one-cell LDS odd step.)"""
+    case = inputs.random_smooth(*dims, seed=sum(dims) + sum(bc), amp=0.05, bc=bc, collision=coll)
+    out = []
+    for staged in (True, False):
+        say(f"FP16 {dims} bc={bc} coll={coll} odd_lds={staged}")
+        with binding.Solver(case.params, storage=binding.LBM_STORE_F16, odd_lds=staged) as s:
+            s.init(case.Q0)
+            s.step(5, 2)
+            f, st = s.populations()
+            recs, status = s.diagnostics()
+        out.append((f, recs, status))
+    (fa, ra, sa), (fb, rb, sb) = out
+    assert sa == sb == binding.LBM_OK and len(ra) == len(rb) == 3  # steps 0, 2, 4
+    assert np.array_equal(fa, fb)
+    for a, b in zip(ra, rb):
+        for key in ("Ek", "eps_s", "eps_d"):
+            assert a[key] == pytest.approx(b[key], rel=1e-5, abs=1e-30), key
