@@ -272,8 +272,12 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
            "fp16_share": sum(r.storage for r in trace) / count}
 
     failures = {}
+    progress = {"leg": "", "done": 0}  # long traces report every 100 results on stderr
 
     def finite(req, Q):
+        progress["done"] += 1
+        if count >= 200 and progress["done"] % 100 == 0:
+            print(f"serve {progress['leg']}: {progress['done']}/{count} results", file=sys.stderr, flush=True)
         ok = bool(np.isfinite(Q).all())
         if not ok:
             failures[req.rid] = {"kind": req.kind, "shape": list(req.case.shape), "steps": req.steps,
@@ -283,6 +287,7 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
         return ok
 
     def batched(storage_override):
+        progress.update(leg="batched" if storage_override is None else "batched fp32", done=0)
         with binding.Batch(budget_bytes, max_instances=4096, max_tiles=1 << 22, graph_steps=chunk,
                            stream=stream.cuda_stream) as b:
             srv = serve.Server(b, arena_bytes=budget_bytes, chunk_steps=chunk, result_handler=finite,
@@ -301,6 +306,7 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
     def fp32_solver(params):
         return binding.Solver(params, stream=stream.cuda_stream)
 
+    progress.update(leg="sequential fp32", done=0)
     st2 = serve.serve_sequential(trace, fp32_solver, result_handler=finite, sync=torch.cuda.synchronize)
     out["sequential_fp32"] = st2.summary()
     out["speedup_solves_per_s"] = out["batched"]["solves_per_s"] / out["sequential_fp32"]["solves_per_s"]
