@@ -6,15 +6,18 @@
 //               reduction to one partial per block) and an optional source term
 //   k_step_odd_tiles  the odd half step over linear tiles of cells with the +-x
 //               populations shifted in LDS, so every HBM access stays aligned
+//   k_step_even_pairs, k_step_odd_row_pairs  FP16 even and odd half steps with
+//               two consecutive cells per lane (4-byte accesses) on large grids
 //   k_finalize  deterministic reduction of the per-block partials into one record
 //   k_init      equilibrium populations from the conserved fields
 //   k_gather    parity-aware readout: canonical populations or conserved moments
 //   k_scatter   parity-aware write of canonical populations (checkpoint restore)
 //   k_copy      streaming copy used to measure achievable HBM bandwidth
 //
-// One lane owns one cell; a block covers `blockDim.x` consecutive cells of one
-// x-row, so every wave reads and writes 64 consecutive elements of each of the 35
-// arrays (coalesced).  The update is memory-bound (no contraction, no MFMA).
+// One lane owns one cell (two in the pair kernels); a block covers `blockDim.x`
+// consecutive cells, so every wave reads and writes 64 consecutive elements of each
+// of the 35 arrays (coalesced).  The update is memory-bound (no contraction, no
+// MFMA).
 #include <hip/hip_runtime.h>
 
 #include "grlbm_device.hpp"
