@@ -267,6 +267,8 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
     work = sum(r.case.cells * r.steps for r in trace)
     out = {"requests": count, "rate_per_s": rate, "seed": seed, "budget_bytes": budget_bytes,
            "admission": "largest work first among arrived requests, any request waiting over 2 s first",
+           "divergence": "batched: checked every 200 steps, a diverged request is retired as failed at once; "
+                         "sequential: every request runs to its step count",
            "offered_glup": work / 1e9,
            "mix": {k: sum(1 for r in trace if r.kind == k) for k in ("sod", "tgv", "becker")},
            "fp16_share": sum(r.storage for r in trace) / count}
@@ -274,17 +276,21 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
     failures = {}
     progress = {"leg": "", "done": 0}  # long traces report every 100 results on stderr
 
-    def finite(req, Q):
+    def failed(req):
+        failures[req.rid] = {"kind": req.kind, "shape": list(req.case.shape), "steps": req.steps,
+                             "storage": req.storage,
+                             **{k: req.case.meta[k] for k in ("mach", "left", "right", "r") if k in req.case.meta}}
+
+    def finished(req, ok):
         progress["done"] += 1
         if count >= 200 and progress["done"] % 100 == 0:
             print(f"serve {progress['leg']}: {progress['done']}/{count} results", file=sys.stderr, flush=True)
-        ok = bool(np.isfinite(Q).all())
         if not ok:
-            failures[req.rid] = {"kind": req.kind, "shape": list(req.case.shape), "steps": req.steps,
-                                 "storage": req.storage,
-                                 **{k: req.case.meta[k] for k in ("mach", "left", "right", "r")
-                                    if k in req.case.meta}}
+            failed(req)
         return ok
+
+    def finite(req, Q):
+        return finished(req, bool(np.isfinite(Q).all()))
 
     def batched(storage_override):
         progress.update(leg="batched" if storage_override is None else "batched fp32", done=0)
@@ -292,7 +298,8 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
                            stream=stream.cuda_stream) as b:
             srv = serve.Server(b, arena_bytes=budget_bytes, chunk_steps=chunk, result_handler=finite,
                                sync=torch.cuda.synchronize, max_active_cells=max_active_cells,
-                               storage_override=storage_override)
+                               storage_override=storage_override,
+                               failure_handler=lambda req: finished(req, False))
             return srv.serve(trace)
 
     # storage as requested (FP16 for about half the requests), then every request in

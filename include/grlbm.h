@@ -74,7 +74,7 @@ typedef struct {
   double sensor_gain;          /* g of the compression sensor                           */
   double J_min;                /* dead band of the sensor                               */
   double omega_min;            /* rate the sensor relaxes towards                       */
-  double rho_min, p_min;       /* positivity floors (Algorithm 1, line 2)               */
+  double rho_min, p_min;       /* positivity floors (Algorithm 1, primitives)          */
   double rho_ref, E_ref;       /* reference state of the equilibrium shift              */
 } lbm_params;
 
@@ -197,7 +197,7 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t trial_steps, lbm_launch* best, flo
 /* Source term S of eq. 1 for the following steps: S_dev points to device memory
  * S[5][nz][ny][nx] (FP32, lattice units per step, field order rho, rho u_x,
  * rho u_y, rho u_z, E), projected onto the lattice weights and added to the
- * post-collision populations of every step (Algorithm 1, last line:
+ * post-collision populations of every step (the collision of Algorithm 1:
  * f*_ki += w_i S_k).  The caller owns the array, keeps it alive while steps that
  * use it are in flight, and may rewrite it between steps in stream order (a
  * time-dependent source is evaluated once per step).  NULL switches the source
@@ -270,6 +270,18 @@ lbm_status lbm_batch_moments(lbm_batch* b, int32_t id, double* Q_out);
 /* Canonical populations of an instance and its completed steps, as
  * lbm_get_populations (synchronises). */
 lbm_status lbm_batch_populations(lbm_batch* b, int32_t id, float* f_out, int64_t* step);
+
+/* Divergence check for early retirement (the failure of a time-marching scheme
+ * is a state that is no longer finite; a diverged instance otherwise occupies the
+ * device until its step count).  Reports the live instances whose rest
+ * population of some field (slot 0 of each of the five fields, every cell) holds
+ * an infinity or a NaN.  Slot 0 of field k after a step sums all of the cell's
+ * field-k populations (the collision of Algorithm 1), so a non-finite population of any
+ * field appears there one step later.  Up to max ids go to ids in ascending order
+ * (ids may be NULL when max is 0); *count receives the number of such instances,
+ * which may exceed max.  Reads 5 of the 35 arrays of every live instance;
+ * synchronises the stream.  EINVAL on a NULL batch or count, or a bad id buffer. */
+lbm_status lbm_batch_nonfinite(lbm_batch* b, int32_t* ids, int32_t max, int32_t* count);
 
 /* Release an instance's arena space and descriptor (synchronises first). */
 lbm_status lbm_batch_remove(lbm_batch* b, int32_t id);

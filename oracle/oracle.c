@@ -24,7 +24,7 @@
  *   9. regularized collision with reduced rate omega_h, or BGK (Sec. 2.2, 2.5)
  *  10. exact on-lattice push streaming into a second buffer
  * With a source S of eq. 1 (ora_step_src) the post-collision populations gain
- * w_i S_k before streaming (Algorithm 1, last line).  ora_mms_source writes the
+ * w_i S_k before streaming (the collision of Algorithm 1).  ora_mms_source writes the
  * source of the manufactured solution of Sec. 3.1 (eq. 8), derived by hand from
  * eq. 2 with constant mu and kappa.
  *
@@ -184,7 +184,7 @@ static int ora_solve(int n, double A[15][15], double b[15], double x[15]) {
 }
 
 /* ------------------------------------------------------- primitives and fluxes */
-/* Algorithm 1 line 2: rho and p floored; u = rho u / rho_floored, T = p/rho. */
+/* Algorithm 1, primitives: rho and p floored; u = rho u / rho_floored, T = p/rho. */
 static void ora_primitives(const ora_params* P, const double Q[5], double* rho_f, double u[3],
                            double* k2, double* p, double* T) {
   double r = Q[0] > P->rho_min ? Q[0] : P->rho_min;
@@ -222,7 +222,7 @@ void ora_collide(const ora_params* P, const double* f_in, double* f_out, ora_cel
   memset(I, 0, sizeof(*I));
   const double g1 = P->gamma - 1.0;
 
-  /* line 1: conserved moments and first moments */
+  /* conserved moments and first moments */
   for (int k = 0; k < 5; ++k) {
     double q = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
     for (int i = 0; i < 7; ++i) {
@@ -237,7 +237,7 @@ void ora_collide(const ora_params* P, const double* f_in, double* f_out, ora_cel
     I->J[k][1] = j1;
     I->J[k][2] = j2;
   }
-  /* line 2: primitives with positivity floors */
+  /* primitives with positivity floors */
   ora_primitives(P, I->Q, &I->rho_f, I->u, &I->k2, &I->p, &I->T);
   const double rho = I->rho_f;
   const double ratio = ora_mu_ratio(P, I->T);
@@ -245,7 +245,7 @@ void ora_collide(const ora_params* P, const double* f_in, double* f_out, ora_cel
   I->kappa = P->kappa_ref * ratio;
   I->nu = I->mu / rho;
 
-  /* line 3: non-equilibrium first moment against the advective flux (eq. 3) */
+  /* non-equilibrium first moment against the advective flux (eq. 3) */
   ora_flux_adv(I->Q, I->u, I->p, I->Phi_adv);
   for (int k = 0; k < 5; ++k)
     for (int c = 0; c < 3; ++c) {
@@ -253,7 +253,7 @@ void ora_collide(const ora_params* P, const double* f_in, double* f_out, ora_cel
       I->gradQ_tilde[k][c] = -I->Pi[k][c] * P->omega[k] / ORA_CS2; /* 1/tau = omega */
     }
 
-  /* line 4: grad Q = R grad Q~ with R = (I - cs^-2 diag(omega) M)^-1 (eq. 4) */
+  /* reconstruction: grad Q = R grad Q~ with R = (I - cs^-2 diag(omega) M)^-1 (eq. 4) */
   ora_assemble_M(P, rho, I->u, I->T, I->mu, I->kappa, I->M);
   {
     double A[15][15], b[15], x[15];
@@ -280,7 +280,7 @@ void ora_collide(const ora_params* P, const double* f_in, double* f_out, ora_cel
                    (0.5 * g1 * I->k2 - I->T) / rho * I->gradQ[0][c];
   }
 
-  /* line 5: compression sensor, s = -div(u)/c_s */
+  /* compression sensor (Sec. 2.5), s = -div(u)/c_s */
   I->theta = I->grad_u[0][0] + I->grad_u[1][1] + I->grad_u[2][2];
   I->s = -I->theta / sqrt(ORA_CS2);
   if (I->theta < 0.0 && I->s > P->J_min) {
@@ -290,13 +290,13 @@ void ora_collide(const ora_params* P, const double* f_in, double* f_out, ora_cel
     I->chi = 0.0;
   }
 
-  /* line 6: Newtonian stress and Fourier flux */
+  /* closures: Newtonian stress and Fourier flux */
   for (int j = 0; j < 3; ++j)
     for (int c = 0; c < 3; ++c)
       I->tau[j][c] = I->mu * (I->grad_u[j][c] + I->grad_u[c][j] - (j == c ? 2.0 / 3.0 * I->theta : 0.0));
   for (int c = 0; c < 3; ++c) I->q[c] = -I->kappa * I->grad_T[c];
 
-  /* line 7: the closures enter the flux moment of the equilibrium (eq. 2) */
+  /* the closures enter the flux moment of the equilibrium (eq. 2) */
   for (int c = 0; c < 3; ++c) {
     I->Phi[0][c] = I->Q[1 + c];
     for (int j = 0; j < 3; ++j)
@@ -305,7 +305,7 @@ void ora_collide(const ora_params* P, const double* f_in, double* f_out, ora_cel
     I->Phi[4][c] = (I->Q[4] + I->p) * I->u[c] - tu + I->q[c];
   }
 
-  /* lines 8-9: collision */
+  /* collision */
   for (int k = 0; k < 5; ++k) {
     const double om = P->omega[k];
     if (P->collision == 1) {

@@ -124,6 +124,7 @@ SIGNATURES = {
     "lbm_batch_moments": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_double)]),
     "lbm_batch_populations": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_float), _P(ctypes.c_int64)]),
     "lbm_batch_remove": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "lbm_batch_nonfinite": (ctypes.c_int, [_vp, _P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_int32)]),
     "lbm_batch_info": (ctypes.c_int, [_vp, _P(lbm_batch_stats)]),
     "lbm_batch_set_tuning": (ctypes.c_int, [_vp, _P(lbm_batch_tuning)]),
     "lbm_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _P(lbm_batch_tuning), _P(ctypes.c_float),
@@ -434,6 +435,13 @@ def lbm_batch_remove(batch: int, inst: int) -> None:
     _check(load().lbm_batch_remove(batch, int(inst)), "lbm_batch_remove")
 
 
+def lbm_batch_nonfinite(batch: int, max_ids: int) -> list:
+    ids = (ctypes.c_int32 * max(1, int(max_ids)))()
+    count = ctypes.c_int32()
+    _check(load().lbm_batch_nonfinite(batch, ids, int(max_ids), ctypes.byref(count)), "lbm_batch_nonfinite")
+    return [int(ids[i]) for i in range(min(count.value, int(max_ids)))]
+
+
 def lbm_batch_info(batch: int) -> dict:
     s = lbm_batch_stats()
     _check(load().lbm_batch_info(batch, ctypes.byref(s)), "lbm_batch_info")
@@ -493,6 +501,10 @@ class Batch:
     def remove(self, i: int) -> None:
         lbm_batch_remove(self.h, i)
         self.shapes.pop(i, None)
+
+    def nonfinite(self) -> list:
+        """Ids of the live instances whose state is no longer finite."""
+        return lbm_batch_nonfinite(self.h, max(1, len(self.shapes)))
 
     def info(self) -> dict:
         return lbm_batch_info(self.h)

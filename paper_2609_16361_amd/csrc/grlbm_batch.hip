@@ -107,6 +107,46 @@ __global__ void k_batch_advance(int64_t* clock, int32_t n) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *clock += n;
 }
 
+// A run of cells [c0, c1) of one instance for the divergence check: element offset
+// of the instance's slot 0 in the arena, elements between its slot arrays, storage,
+// and the index of the instance's flag.
+struct CheckItem {
+  int64_t off;
+  int64_t S;
+  int32_t c0, c1;
+  int32_t f16;
+  int32_t flag;
+};
+constexpr int32_t kCheckRun = 16384;   // cells per item
+constexpr int32_t kCheckBlocks = 16;   // blocks per item (256 lanes, 4 cells each)
+
+// flags[item.flag] = 1 when the rest population (slot 0) of some field holds a
+// non-finite value in the item's cells (exponent bits all ones: an infinity or a
+// NaN, FP32 or FP16).  Slot 0 of field k after a step is a sum over all of the
+// cell's field-k populations before it (Q_k / 4 in the regularized update, f_0 +
+// omega (f_0^eq - f_0) with f_0^eq = Q_k / 4 in BGK), so a non-finite population of
+// any field shows up there one step after it appears.  blockIdx.y picks the item;
+// its kCheckBlocks blocks stride over the run.  Reads 5 of the 35 arrays.
+__global__ void __launch_bounds__(256) k_batch_nonfinite(const char* __restrict__ arena,
+                                                          const CheckItem* __restrict__ items,
+                                                          int32_t* __restrict__ flags) {
+  const CheckItem it = items[blockIdx.y];
+  bool bad = false;
+  for (int32_t c = it.c0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); c < it.c1;
+       c += (int32_t)(gridDim.x * blockDim.x)) {
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) {
+      const int64_t e = it.off + (int64_t)(7 * k) * it.S + c;
+      if (it.f16) {
+        bad |= (reinterpret_cast<const uint16_t*>(arena)[e] & 0x7c00u) == 0x7c00u;
+      } else {
+        bad |= (reinterpret_cast<const uint32_t*>(arena)[e] & 0x7f800000u) == 0x7f800000u;
+      }
+    }
+  }
+  if (bad) flags[it.flag] = 1;  // every writer stores the same value
+}
+
 }  // namespace grlbm
 
 using grlbm::BatchInst;
@@ -142,6 +182,9 @@ struct lbm_batch {
   BatchTile* d_tiles = nullptr;      // kGroups segments of max_tiles
   int32_t* d_ntiles = nullptr;       // kGroups counts
   int64_t* d_clock = nullptr;
+  grlbm::CheckItem* d_check = nullptr;  // items of the divergence check (grown on demand)
+  size_t check_cap = 0;
+  int32_t* d_flags = nullptr;           // one flag per live instance (max_inst)
   std::vector<HostInst> insts;
   int64_t clock = 0;
   int32_t graph_steps = 16;
@@ -408,7 +451,8 @@ lbm_status lbm_batch_create(size_t arena_bytes, int32_t max_instances, int32_t m
   if (hipMalloc((void**)&b->d_insts, sizeof(BatchInst) * (size_t)max_instances) != hipSuccess ||
       hipMalloc((void**)&b->d_tiles, sizeof(BatchTile) * (size_t)max_tiles * kGroups) != hipSuccess ||
       hipMalloc((void**)&b->d_ntiles, sizeof(int32_t) * kGroups) != hipSuccess ||
-      hipMalloc((void**)&b->d_clock, sizeof(int64_t)) != hipSuccess)
+      hipMalloc((void**)&b->d_clock, sizeof(int64_t)) != hipSuccess ||
+      hipMalloc((void**)&b->d_flags, sizeof(int32_t) * (size_t)max_instances) != hipSuccess)
     return bail(fail(LBM_ENOMEM, "hipMalloc of the batch tables failed"));
   const int64_t zero = 0;
   const int32_t zeros[kGroups] = {0, 0, 0, 0};
@@ -551,6 +595,55 @@ lbm_status lbm_batch_populations(lbm_batch* b, int32_t id, float* f_out, int64_t
   (void)hipFree(d);
   if (e != hipSuccess) return fail(LBM_EDEVICE, "population readout failed: %s", hipGetErrorString(e));
   if (step) *step = done;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_nonfinite(lbm_batch* b, int32_t* ids, int32_t max, int32_t* count) {
+  if (!b || !count) return fail(LBM_EINVAL, "NULL argument");
+  if (max < 0 || (max > 0 && !ids)) return fail(LBM_EINVAL, "bad id buffer (max %d)", max);
+  *count = 0;
+  std::vector<grlbm::CheckItem> items;
+  std::vector<int32_t> which;  // flag index -> instance id
+  for (int32_t id = 0; id < (int32_t)b->insts.size(); ++id) {
+    const HostInst& h = b->insts[id];
+    if (!h.live) continue;
+    const int32_t f16 = h.p.storage == LBM_STORE_F16 ? 1 : 0;
+    for (int32_t c0 = 0; c0 < h.d.cells; c0 += grlbm::kCheckRun)
+      items.push_back({h.d.off, h.d.g.S, c0, c0 + std::min(grlbm::kCheckRun, h.d.cells - c0), f16,
+                       (int32_t)which.size()});
+    which.push_back(id);
+  }
+  const int32_t n = (int32_t)which.size();  // at most max_inst flags
+  if (n == 0) return LBM_OK;
+  if (items.size() > b->check_cap) {
+    // no check kernel is in flight: every call ends synchronised
+    const size_t want = std::max(items.size(), 2 * b->check_cap);
+    if (b->d_check) (void)hipFree(b->d_check);
+    b->d_check = nullptr;
+    b->check_cap = 0;
+    if (hipMalloc((void**)&b->d_check, sizeof(grlbm::CheckItem) * want) != hipSuccess)
+      return fail(LBM_ENOMEM, "hipMalloc of %zu check items failed", want);
+    b->check_cap = want;
+  }
+  std::vector<int32_t> flags(n, 0);
+  HIP_TRY(hipMemcpyAsync(b->d_check, items.data(), sizeof(grlbm::CheckItem) * items.size(), hipMemcpyHostToDevice,
+                         b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_flags, flags.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, b->stream));
+  constexpr size_t kMaxGridY = 65535;
+  for (size_t i0 = 0; i0 < items.size(); i0 += kMaxGridY) {
+    const size_t m = std::min(kMaxGridY, items.size() - i0);
+    hipLaunchKernelGGL(grlbm::k_batch_nonfinite, dim3(grlbm::kCheckBlocks, (unsigned)m), dim3(256), 0, b->stream,
+                       (const char*)b->arena, b->d_check + i0, b->d_flags);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipMemcpyAsync(flags.data(), b->d_flags, sizeof(int32_t) * n, hipMemcpyDeviceToHost, b->stream));
+  // the host vectors above must outlive the copies
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int32_t i = 0; i < n; ++i) {
+    if (!flags[i]) continue;
+    if (*count < max) ids[*count] = which[i];
+    ++*count;
+  }
   return LBM_OK;
 }
 
@@ -729,6 +822,8 @@ lbm_status lbm_batch_destroy(lbm_batch* b) {
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_ntiles) (void)hipFree(b->d_ntiles);
   if (b->d_clock) (void)hipFree(b->d_clock);
+  if (b->d_check) (void)hipFree(b->d_check);
+  if (b->d_flags) (void)hipFree(b->d_flags);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return st;

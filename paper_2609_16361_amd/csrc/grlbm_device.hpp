@@ -192,7 +192,7 @@ struct CellDiag {
 // the arithmetic in between is the same FP32 arithmetic as without scaling.
 template <int COLL, bool DIAG, bool SCALED = false>
 __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* d) {
-  // line 1: moments (the shift cancels in the first moments)
+  // moments (Algorithm 1; the shift cancels in the first moments)
   float dq[5], J[5][3];
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -212,7 +212,7 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
   const float m0 = dq[1], m1 = dq[2], m2 = dq[3];
   const float E = c.E_ref + dq[4];
 
-  // line 2: primitives with positivity floors
+  // primitives with positivity floors
   const float rf = fmaxf(rho, c.rho_min);
   const float ir = rcp(rf);
   const float u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
@@ -229,7 +229,7 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
   const float kap = c.kappa_ref * ratio;
   const float nu = mu * ir;
 
-  // line 3: direct gradients -Pi / (c_s^2 tau) = -4 omega (J - Phi_adv)  (eq. 3)
+  // direct gradients -Pi / (c_s^2 tau) = -4 omega (J - Phi_adv)  (eq. 3)
   const float a_r = -4.0f * c.om[0], a_m = -4.0f * c.om[1], a_e = -4.0f * c.om[2];
   const float gr0 = a_r * (J[0][0] - m0);
   const float gr1 = a_r * (J[0][1] - m1);
@@ -250,7 +250,7 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) gE[cc] = a_e * (J[4][cc] - H * u[cc]);
 
-  // line 4: reconstruction.  Momentum block: scale the symmetric-deviatoric part.
+  // reconstruction (eq. 4).  Momentum block: scale the symmetric-deviatoric part.
   const float tr = X[0][0] + X[1][1] + X[2][2];
   const float beta = 8.0f * nu * c.om[1];
   const float fb = beta * rcp(1.0f + beta);
@@ -294,7 +294,7 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) gT[cc] = gTf * (gradE[cc] - Bt[cc]) + cT * gr[cc];
 
-  // line 5: compression sensor, s = -div(u)/c_s with c_s = 1/2
+  // compression sensor (Sec. 2.5), s = -div(u)/c_s with c_s = 1/2
   const float theta = tr * ir;  // the deviatoric correction is traceless
   const float s = -2.0f * theta;
   float chi = 0.0f;
@@ -302,7 +302,7 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
     chi = (theta < 0.0f && s > c.J_min) ? fminf(1.0f, fmaxf(0.0f, c.gain * s)) : 0.0f;
   }
 
-  // line 6: Newtonian stress tau = mu (grad u + grad u^T - 2/3 div u I), q = -kappa grad T
+  // closures: Newtonian stress tau = mu (grad u + grad u^T - 2/3 div u I), q = -kappa grad T
   const float mir = mu * ir;
   float tau[3][3];
 #pragma unroll
@@ -311,7 +311,7 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
     for (int cc = 0; cc < 3; ++cc)
       tau[j][cc] = mir * (Xs[j][cc] + Xs[cc][j]) - (j == cc ? (2.0f / 3.0f) * mu * theta : 0.0f);
 
-  // line 7: full flux of eq. 2 in the equilibrium
+  // full flux of eq. 2 in the equilibrium
   float Phi[5][3];
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
@@ -333,7 +333,7 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
     for (int k = 0; k < 5; ++k) d->dq[k] = dq[k];
   }
 
-  // lines 8-9: collision
+  // collision
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     const float om = c.om[k == 0 ? 0 : (k == 4 ? 2 : 1)];
@@ -377,7 +377,7 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
 
 // ---------------------------------------------------------------- source term
 // The source S of eq. 1 projected onto the lattice weights and added to the
-// post-collision populations (Algorithm 1, last line): f*_ki += w_i S_k.  src holds
+// post-collision populations (the collision of Algorithm 1): f*_ki += w_i S_k.  src holds
 // the step's source per cell, src[5][N] with N the cell count, lattice units.
 __device__ __forceinline__ void add_source(float f[kPop], const float* __restrict__ src, int64_t N,
                                            int64_t n) {

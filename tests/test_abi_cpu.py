@@ -152,3 +152,4 @@ def test_null_arguments():
     best = binding.lbm_launch()
     assert lib.lbm_autotune(None, 10, ctypes.byref(best), None, None, None, 0, None) == binding.LBM_EINVAL
     assert lib.lbm_get_launch(None, ctypes.byref(best)) == binding.LBM_EINVAL
+    assert lib.lbm_batch_nonfinite(None, None, 0, ctypes.byref(cnt)) == binding.LBM_EINVAL

@@ -131,6 +131,36 @@ def test_batch_remove_and_reuse():
         assert info["live_instances"] == 2 and info["active_instances"] == 0
 
 
+def test_batch_nonfinite_flags_diverged_instances():
+    """lbm_batch_nonfinite reports exactly the instances whose stored rest
+    populations (slot 0 of each field) are not all finite: a Mach 1.5 vortex on 16^3
+    (its isothermal initial pressure is negative; the FP64 oracle's state stops
+    being finite at step 12), in FP32 and FP16 storage, next to smooth states that
+    stay finite."""
+    bad = inputs.tgv(n=16, mach=1.5, steps=60, diag_every=0)
+    g0 = inputs.random_smooth(40, 5, 4, seed=8, amp=0.05)
+    g1 = inputs.random_smooth(30, 6, 4, seed=9, amp=0.05, bc=(0, 1, 0))
+    with binding.Batch(1 << 28) as b:
+        ids = {"bad32": b.add(bad.params, bad.Q0, 60),
+               "good32": b.add(g0.params, g0.Q0, 60),
+               "bad16": b.add(bad.params, bad.Q0, 60, storage=binding.LBM_STORE_F16),
+               "good16": b.add(g1.params, g1.Q0, 60, storage=binding.LBM_STORE_F16)}
+
+        def expected():
+            return sorted(i for i in ids.values()
+                          if not np.isfinite(b.populations(i)[0][[0, 7, 14, 21, 28]]).all())
+
+        assert b.nonfinite() == expected()
+        b.run(60)
+        flagged = b.nonfinite()
+        say(f"flagged after 60 steps: {[k for k, i in ids.items() if i in flagged]}")
+        assert flagged == expected()
+        assert ids["bad32"] in flagged
+        assert ids["good32"] not in flagged and ids["good16"] not in flagged
+        b.remove(ids["bad32"])
+        assert ids["bad32"] not in b.nonfinite()
+
+
 def test_batch_arena_full():
     c = inputs.random_smooth(64, 8, 8, seed=1)
     need = binding.lbm_state_bytes(binding.make_params(c.params))

@@ -167,7 +167,7 @@ def test_exact_gradient_recovery(seed, omega):
     gu, gT = grad_prims(Q, gradQ)
     np.testing.assert_allclose(info["grad_u"], gu, rtol=1e-9, atol=1e-12 * np.abs(gu).max())
     np.testing.assert_allclose(info["grad_T"], gT, rtol=1e-9, atol=1e-12 * np.abs(gT).max())
-    # the closures enter the equilibrium flux (Algorithm 1, line 7)
+    # the closures enter the equilibrium flux (Algorithm 1)
     np.testing.assert_allclose(info["Phi"], flux_adv(Q) + flux_diff(prm, Q, gradQ),
                                rtol=1e-10, atol=1e-14)
 
@@ -310,7 +310,7 @@ def test_sutherland_limits():
 
 
 def test_positivity_floors():
-    """Algorithm 1 line 2 and Table 1: rho and p are floored; conservation of the
+    """Algorithm 1 (primitives) and Table 1: rho and p are floored; conservation of the
     (unfloored) zeroth moment is kept."""
     prm = params(rho_min=1e-4, p_min=1e-7)
     Q = np.array([1e-6, 1e-8, 0.0, 0.0, 1e-12])

@@ -9,7 +9,7 @@ Pins:
     conserved fields at t = 1 on 8^3, 16^3, 32^3, with the relaxation tied to the
     time step close to 2 so that these grids are already asymptotic;
   * a source added after the collision changes the zeroth moment by exactly S and
-    leaves the first moment alone (Algorithm 1, last line).
+    leaves the first moment alone (the collision of Algorithm 1).
 """
 import math
 

@@ -183,3 +183,70 @@ def test_riemann_max_speed_sod():
     # p* = 0.30313, u* = 0.92745)
     s = inputs.riemann_max_speed((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
     assert s == pytest.approx(2.19, abs=0.02)
+
+
+class FakeDivergingBatch(FakeBatch):
+    """As FakeBatch; the instance added k-th stops being finite after diverge[k]
+    completed steps."""
+
+    def __init__(self, clock, diverge, dt=1e-3):
+        super().__init__(clock, dt)
+        self.diverge, self.order = diverge, {}
+
+    def add(self, params, Q, steps, storage=0):
+        i = super().add(params, Q, steps, storage)
+        self.order[i] = len(self.order)
+        return i
+
+    def nonfinite(self):
+        return [i for i, v in self.inst.items()
+                if self.order[i] in self.diverge and v[0] >= self.diverge[self.order[i]]]
+
+
+@pytest.mark.parametrize("stop", [True, False])
+def test_diverged_request_retired_early(stop):
+    """A request whose state stops being finite is retired as failed after the chunk
+    in which that happened (its memory freed for the next request), not at its step
+    count; the result handler is not called for it, the failure handler is.  With
+    the check off it runs to its step count."""
+    clk = FakeClock()
+    fb = FakeDivergingBatch(clk, diverge={0: 25})
+    reqs = [make_req(0, 0.0, 1600, 1000), make_req(1, 0.0005, 1600, 100)]
+    one = serve.state_bytes(reqs[0].case.params, 0)
+    seen, failed = [], []
+
+    def handler(req, Q):
+        seen.append(req.rid)
+        return req.rid != 0          # a diverged state is not a result
+
+    srv = serve.Server(fb, arena_bytes=one, chunk_steps=10, clock=clk, order="fifo", result_handler=handler,
+                       stop_diverged=stop, check_steps=10, failure_handler=failed.append)
+    st = srv.serve(reqs)
+    s = st.summary()
+    o0, o1 = st.outcomes
+    assert not o0.ok and o1.ok and s["failed"] == 1
+    if stop:
+        assert s["stopped_diverged"] == 1 and [r.rid for r in failed] == [0] and seen == [1]
+        # retired at the end of the chunk holding step 25, so the second request
+        # (which waited for its memory) starts after 30 steps, not 1000
+        assert o0.completed == pytest.approx(30 * fb.dt)
+        assert o1.admitted == pytest.approx(30 * fb.dt)
+    else:
+        assert s["stopped_diverged"] == 0 and failed == [] and seen == [0, 1]
+        assert o0.completed == pytest.approx(1000 * fb.dt)
+        assert o1.admitted == pytest.approx(1000 * fb.dt)
+
+
+def test_divergence_check_interval():
+    """With check_steps = 25 and chunks of 10 steps the check follows every third
+    chunk: an instance that diverges at step 5 is retired after 30 steps."""
+    clk = FakeClock()
+    fb = FakeDivergingBatch(clk, diverge={0: 5})
+    calls = []
+    check = fb.nonfinite
+    fb.nonfinite = lambda: calls.append(clk.t) or check()
+    srv = serve.Server(fb, arena_bytes=1 << 30, chunk_steps=10, clock=clk, check_steps=25)
+    st = srv.serve([make_req(0, 0.0, 1600, 1000)])
+    assert not st.outcomes[0].ok and st.stopped == 1
+    assert st.outcomes[0].completed == pytest.approx(30 * fb.dt)
+    assert calls == [pytest.approx(30 * fb.dt)]
