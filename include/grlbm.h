@@ -121,8 +121,9 @@ lbm_status lbm_init_fields(lbm_ctx* ctx, const double* Q);
 /* Same, with Q already in device memory (float64, same layout); asynchronous for
  * FP32 storage.  FP16 storage keeps each field's shifted populations times a power
  * of two chosen here from the initial state (largest |value| mapped into
- * [512, 1024)), which keeps the values in FP16's normal range; choosing it
- * synchronises the stream.  The scale is invisible through this ABI. */
+ * [32, 64), leaving 1024x headroom for populations that grow during the run),
+ * which keeps the values in FP16's normal range; choosing it synchronises the
+ * stream.  The scale is invisible through this ABI. */
 lbm_status lbm_init_fields_device(lbm_ctx* ctx, const double* Q_dev);
 
 /* Enqueue n >= 0 collide-and-stream steps on the context's stream (asynchronous).

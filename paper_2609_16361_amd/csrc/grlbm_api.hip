@@ -133,7 +133,7 @@ void set_storage_scales(Coll& c, const unsigned maxabs_bits[5]) {
     int e = 0;
     if (m > 0.0f) {
       std::frexp(m, &e);  // m = f * 2^e, f in [0.5, 1)
-      e = 10 - e;         // m * 2^e in [512, 1024)
+      e = 6 - e;          // m * 2^e in [32, 64)
       e = std::min(std::max(e, -100), 100);
     }
     c.sc[k] = std::ldexp(1.0f, e);

@@ -80,8 +80,12 @@ hipError_t launch_scatter(void* F, bool f16, const Grid& g, const Coll& c, int64
 hipError_t launch_init_maxabs(const Grid& g, const Coll& c, const double* Q, int64_t N, unsigned* maxabs,
                               hipStream_t s);
 hipError_t launch_maxabs_pops(const float* f, int64_t N, unsigned* maxabs, hipStream_t s);
-// FP16 storage: pick power-of-two scales so that each field's largest |g| maps into
-// [512, 1024) (64x headroom below the FP16 maximum, 2^-24 of it before subnormals).
+// FP16 storage: pick power-of-two scales so that each field's largest initial |g|
+// maps into [32, 64): 1024x headroom below the FP16 maximum for populations that
+// grow during the run (a nearly uniform initial field gets a large scale, and a
+// shock can raise its populations almost a hundredfold), and 2^-19 of it before
+// subnormals.  A power-of-two scale leaves the mantissa bits, hence the stochastic
+// rounding of every normal value, unchanged.
 void set_storage_scales(Coll& c, const unsigned maxabs_bits[5]);
 // Scales from the initial fields Q (device) or from canonical populations f
 // (device); synchronises the stream to read the maxima back.
