@@ -60,6 +60,9 @@ class ServeStats:
     max_active: int = 0
     peak_bytes: int = 0
     stopped: int = 0            # failed requests retired early by the divergence check
+    # one entry per chunk: (start, end, resident instances, resident cells); the
+    # instances that reached their step count earlier in the chunk are included
+    timeline: list = field(default_factory=list)
 
     def summary(self) -> dict:
         done = [o for o in self.outcomes if o.ok]
@@ -76,6 +79,9 @@ class ServeStats:
                 "latency_p99_s": float(np.percentile(lat, 99)),
                 "latency_mean_s": float(np.mean(lat)),
                 "stopped_diverged": self.stopped,
+                "resident_cells_mean": (sum((b - a) * c for a, b, _, c in self.timeline) /
+                                        max(sum(b - a for a, b, _, _ in self.timeline), 1e-12)
+                                        if self.timeline else 0.0),
                 "chunks": self.chunks, "max_active": self.max_active,
                 "peak_arena_bytes": self.peak_bytes, "wall_s": self.wall_s}
 
@@ -185,10 +191,12 @@ class Server:
                 continue
             # one chunk (a graph replay) for everything on the device; an instance that
             # reaches its step count inside the chunk stays frozen there
+            t_start = self.clock() - t0
             self.b.run(self.chunk)
             st.chunks += 1
             self.sync()
             tnow = self.clock() - t0
+            st.timeline.append((t_start, tnow, len(active), used_cells))
             for iid in [i for i in active if self.b.query(i)[1]]:
                 r, nb = active.pop(iid)
                 Q = self.b.moments(iid)

@@ -250,3 +250,18 @@ def test_divergence_check_interval():
     assert not st.outcomes[0].ok and st.stopped == 1
     assert st.outcomes[0].completed == pytest.approx(30 * fb.dt)
     assert calls == [pytest.approx(30 * fb.dt)]
+
+
+def test_timeline_of_resident_cells():
+    """One timeline entry per chunk with the resident instances and cells while it
+    ran; the summary's time-weighted mean of resident cells follows from it."""
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    reqs = [make_req(0, 0.0, 1600, 40), make_req(1, 0.0, 3200, 20)]
+    srv = serve.Server(fb, arena_bytes=1 << 30, chunk_steps=10, clock=clk)
+    st = srv.serve(reqs)
+    assert len(st.timeline) == st.chunks == 4
+    assert [(n, c) for _, _, n, c in st.timeline] == [(2, 4800), (2, 4800), (1, 1600), (1, 1600)]
+    for a, b, _, _ in st.timeline:
+        assert b - a == pytest.approx(10 * fb.dt)
+    assert st.summary()["resident_cells_mean"] == pytest.approx((4800 + 4800 + 1600 + 1600) / 4)
