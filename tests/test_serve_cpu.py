@@ -265,3 +265,18 @@ def test_timeline_of_resident_cells():
     for a, b, _, _ in st.timeline:
         assert b - a == pytest.approx(10 * fb.dt)
     assert st.summary()["resident_cells_mean"] == pytest.approx((4800 + 4800 + 1600 + 1600) / 4)
+
+
+def test_state_bytes_mirrors_the_library():
+    """The server's admission arithmetic (serve.state_bytes, no device call) gives
+    the bytes lbm_state_bytes reports, for FP32 and FP16, with and without pads."""
+    from paper_2609_16361_amd import binding
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        nx, ny, nz = (int(v) for v in rng.integers(1, 300, size=3))
+        pad = int(rng.choice([0, 1, 37, 4096]))
+        for storage in (0, 1):
+            params = dict(inputs.base_params(nx, ny, nz, (0, 0, 0), mu=1e-3), layout_pad=pad)
+            p = binding.make_params(params)
+            p.storage = storage
+            assert serve.state_bytes(params, storage) == binding.lbm_state_bytes(p), (nx, ny, nz, pad, storage)
