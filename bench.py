@@ -26,9 +26,21 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 BYTES_PER_LUP_F32 = 280.0    # 35 populations x 4 B, read and written once
 
 
+def _oracle_rate(params, f, steps):
+    """Oracle cell updates per second over `steps` steps after one warm-up step."""
+    import oracle
+    f, _ = oracle.run(params, f, 1)
+    t0 = time.perf_counter()
+    oracle.run(params, f, steps)
+    return oracle.cells(params) * steps / (time.perf_counter() - t0)
+
+
 def cpu_baseline(target_s=15.0):
     """The oracle as it stands on a slab of the 256^3 workload (full x-y planes,
-    32 z-planes, periodic), stepped for about target_s of wall time."""
+    32 z-planes, periodic), stepped for about target_s of wall time; then the oracle's
+    rate on the other configurations: the Sod tube in full (256x4x4, 400 steps), the
+    first two tubes of the Becker batch (50 steps) and the 128^3 vortex of the
+    precision study (3 steps)."""
     import numpy as np
     import oracle
     from paper_2609_16361_amd import inputs
@@ -55,6 +67,25 @@ def cpu_baseline(target_s=15.0):
         glups_1 = cells * 2 / (time.perf_counter() - t0) / 1e9
     finally:
         oracle.set_num_threads(cores)
+    del f
+    configs = {}
+    sod = inputs.sod(n=256, ny=4, nz=4, steps=400)
+    t0 = time.perf_counter()
+    oracle.run(sod.params, oracle.init(sod.params, sod.Q0), sod.steps)
+    configs["sod_256x4x4_400_steps"] = {"mlups": sod.cells * sod.steps / (time.perf_counter() - t0) / 1e6,
+                                        "sample": "full run"}
+    tubes = inputs.becker_batch(2)
+    t_b, lup_b = 0.0, 0
+    for c in tubes:
+        t0 = time.perf_counter()
+        oracle.run(c.params, oracle.init(c.params, c.Q0), 50)
+        t_b += time.perf_counter() - t0
+        lup_b += c.cells * 50
+    configs["becker_batch"] = {"mlups": lup_b / t_b / 1e6,
+                               "sample": f"first 2 of the 64 tubes ({sum(c.cells for c in tubes)} cells), 50 steps"}
+    v = inputs.tgv(n=128, steps=3)
+    rate = _oracle_rate(v.params, oracle.init(v.params, v.Q0), 3)
+    configs["tgv_128"] = {"mlups": rate / 1e6, "sample": "128^3, 3 steps after 1 warm-up step"}
     model = None
     try:
         for line in open("/proc/cpuinfo"):
@@ -66,7 +97,7 @@ def cpu_baseline(target_s=15.0):
     return {"value": glups, "unit": "GLUP/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, 256x256x32 slab of the 256^3 cTGV initial field, {steps} steps "
                       f"after 3 warm-up steps, {dt:.1f} s",
-            "one_thread_value": glups_1, "cpu_model": model}
+            "one_thread_value": glups_1, "cpu_model": model, "other_configs": configs}
 
 
 def becker_linf(case, Q):
@@ -443,6 +474,9 @@ def main():
         launch["autotuned"] = tuned
 
     glups = cells * args.steps / (ms * 1e-3) / 1e9
+    # lbm_step reduces the diagnostics on the steps t with t % diag_every == 0
+    diag_timed = (sum(1 for t in range(args.warmup, args.warmup + args.steps) if t % args.diag_every == 0)
+                  if args.diag_every > 0 else 0)
     avg_launch_ms = ms / args.steps
     achieved_gbs = bytes_per_lup * cells / (avg_launch_ms * 1e-3) / 1e9
 
@@ -466,8 +500,9 @@ def main():
         "config": {"workload": f"compressible Taylor-Green vortex {args.n}^3 periodic "
                                f"{'FP16-storage' if args.fp16 else 'FP32'}, Mach 1.25, "
                                f"Re 1600, regularized collision + sensor, diagnostics every "
-                               f"{args.diag_every} steps",
+                               f"{args.diag_every} steps ({diag_timed} of the {args.steps} timed steps)",
                    "cells": cells, "steps": args.steps, "diag_every": args.diag_every,
+                   "diag_steps_timed": diag_timed,
                    **launch,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,

@@ -148,15 +148,36 @@ def mms_exact(case: Case, t) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------- Sod
-def sod(n=256, ny=4, nz=4, r=0.128, t_end=0.2, left=(1.0, 1.0), right=(0.125, 0.1),
+# --------------------------------------------------------------- time step (CFL)
+# Sec. 2.6 and Table 1 state a Courant number and write it as dt/dx.  Taken
+# literally, the Becker ceiling of about 0.7 would move the Mach 2 upstream flow 1.4
+# cells per step.  The reading used throughout: the Courant number of the fastest
+# characteristic, CFL = lambda_max dt/dx with lambda_max the largest |u| + c of the
+# flow (of the exact solution where the case has one, else of the initial state).
+# With Table 1's Sod value 0.35 the oracle then lands within 10% of every error of
+# Table 3 (N = 750 to 6000), while the literal dt/dx = 0.35 diverges.
+# Near omega = 2 this reading puts Table 1's vortex point (0.1) outside the linear
+# stability limit of the regularized collision, about 0.41 sqrt(2 - omega) cells per
+# step (0.003 at omega = 1.99996), and that run diverges within a few hundred steps;
+# the cases run near omega = 2 (vortex, Becker, whose Table 1 entry is only the
+# stability map) take 0.05, at which the 256^3 vortex stays finite to t_c = 10.
+CFL_SOD = 0.35
+CFL_NEAR_TWO = 0.05
+
+
+def sod(n=256, ny=4, nz=4, r=None, t_end=0.2, steps=None, left=(1.0, 1.0), right=(0.125, 0.1),
         gamma=1.4, Pr=0.71, mu=1e-6, omega=1.40, sensor_gain=20.0, J_min=3e-3,
-        omega_min=1.0) -> Case:
+        omega_min=1.0, cfl=None) -> Case:
     """Sod shock tube on [0,1] (Sec. 3.2): left/right = (rho, p), u = 0, cell
     centres x = (i + 1/2)/n, zero gradient at both x ends, periodic in y and z.
-    r = dt/dx is chosen so that the fastest wave (|u| + c <= 2.2) moves at most
-    0.28 cells per step, below the D3Q7 sound speed 1/2; at n = 256, 400 steps
-    reach t = 0.2."""
+    Unless r = dt/dx is given, r = cfl / lambda_max with lambda_max the fastest
+    characteristic speed of the exact Riemann solution (2.19 for Sod) and cfl the
+    Table 1 value 0.35 (CFL_SOD), so r = 0.160.  The run ends at t_end unless a step
+    count is given (at n = 256, t = 0.2 takes 321 steps)."""
     dx = 1.0 / n
+    if r is None:
+        smax = riemann_max_speed((left[0], 0.0, left[1]), (right[0], 0.0, right[1]), gamma)
+        r = (CFL_SOD if cfl is None else cfl) / smax
     x = (np.arange(n) + 0.5) * dx
     rho1 = np.where(x < 0.5, left[0], right[0])
     p1 = np.where(x < 0.5, left[1], right[1])
@@ -168,8 +189,9 @@ def sod(n=256, ny=4, nz=4, r=0.128, t_end=0.2, left=(1.0, 1.0), right=(0.125, 0.
                       mu=mu * r / dx, Pr=Pr, omega=omega, sensor_gain=sensor_gain,
                       J_min=J_min, omega_min=omega_min, p_min=1e-4 * r * r,
                       rho_ref=right[0], E_ref=right[1] * r * r / (gamma - 1.0))
-    steps = int(round(t_end / (r * dx)))
-    return Case("sod", prm, Q, steps, 0,
+    if steps is None:
+        steps = int(round(t_end / (r * dx)))
+    return Case("sod", prm, Q, int(steps), 0,
                 dict(dx=dx, r=r, x=x, t_end=steps * r * dx, left=left, right=right, gamma=gamma))
 
 
@@ -184,12 +206,9 @@ def f_mu_for(n: int) -> float:
     return F_MU[best]
 
 
-TGV_LATTICE_SPEED = 0.05  # peak |u| + c of the initial field in lattice units
-
-
 def tgv(n=256, mach=1.25, Re=1600.0, Pr=0.71, gamma=1.4, r=None, f_mu=None,
         sensor_gain=40.0, J_min=1e-2, omega_min=1.987, steps=2000, diag_every=50,
-        collision=RLB_SENSOR, dims=None, lattice_speed=TGV_LATTICE_SPEED) -> Case:
+        collision=RLB_SENSOR, dims=None, cfl=CFL_NEAR_TWO) -> Case:
     """Compressible Taylor-Green vortex on [0, 2pi)^3 (Sec. 3.3): V0 = rho0 = L0 = 1,
     u = (sin x cos y cos z, -cos x sin y cos z, 0), pressure of the incompressible
     solution p = p0 + (1/16)(cos 2x + cos 2y)(cos 2z + 2) with p0 = c0^2/gamma,
@@ -197,17 +216,14 @@ def tgv(n=256, mach=1.25, Re=1600.0, Pr=0.71, gamma=1.4, r=None, f_mu=None,
     mu_ref = 1/Re at T_ref = T0.  Nodes x_i = i dx, dx = 2 pi / n.  The relaxation
     time follows the background damping rule tau = 1/2 + 4 f_mu nu dt/dx^2.
 
-    Time step: unless r = dt/dx is given, r = lattice_speed / (V0 + c0), i.e. the
-    fastest initial characteristic moves lattice_speed cells per step.  (With the
-    regularized collision near omega = 2 the linearised update grows at grid-scale
-    wavenumbers once the lattice sound and flow speeds are large compared with the
-    viscosity; r = 0.1 diverges within a few hundred steps at 64^3-256^3, 0.05 cells
-    per step stays finite to t_c = 10.)"""
+    Time step: unless r = dt/dx is given, r = cfl / (V0 + c0), i.e. the fastest
+    initial characteristic moves cfl cells per step (CFL_NEAR_TWO: Table 1's 0.1
+    diverges under the regularized collision near omega = 2)."""
     nx, ny, nz = dims if dims is not None else (n, n, n)
     dx = 2.0 * math.pi / n
     c0 = 1.0 / mach
     if r is None:
-        r = lattice_speed / (1.0 + c0)
+        r = cfl / (1.0 + c0)
     p0 = c0 * c0 / gamma
     T0 = p0
     x = np.arange(nx) * dx
@@ -323,13 +339,14 @@ def becker_profile(x, mach, mu, x_shock=0.0, gamma=1.4, rho1=1.0, c1=1.0):
 
 
 def becker(L=1024, mach=2.0, cells_per_front=16.0, ny=4, nz=4, gamma=1.4, omega=1.99,
-           beta_max=4.0, sensor_gain=20.0, J_min=3e-3, omega_min=1.0, u_max=0.05) -> Case:
+           beta_max=4.0, sensor_gain=20.0, J_min=3e-3, omega_min=1.0, cfl=CFL_NEAR_TWO) -> Case:
     """Stationary Becker shock in lattice units, shock frame, centred in an L-cell tube
     with zero-gradient ends (Sec. 3.2 configuration, Pr = 3/4, constant mu).
-    The upstream sound speed is set so that |u1| + c1 = u_max; mu is chosen for the
+    The upstream sound speed is set so that |u1| + c1 = cfl (the fastest
+    characteristic moves cfl cells per step); mu is chosen for the
     requested maximum-slope thickness, capped so that the lattice viscous number
     beta = 2 nu omega / c_s^2 upstream stays <= beta_max (eq. 6)."""
-    c1 = u_max / (mach + 1.0)
+    c1 = cfl / (mach + 1.0)
     mu = becker_mu_for_thickness(mach, cells_per_front, gamma, 1.0, c1)
     beta = 8.0 * mu * omega
     if beta > beta_max:
@@ -432,14 +449,13 @@ def riemann_max_speed(left, right, gamma=1.4):
     return max(speeds)
 
 
-def sod_variant(n, rho_ratio, p_ratio, ny=4, nz=4, lattice_speed=0.28, **kw):
+def sod_variant(n, rho_ratio, p_ratio, ny=4, nz=4, cfl=CFL_SOD, **kw):
     """Sod-type tube with left/right density and pressure ratios (right state 0.125,
-    0.1 scaled by the ratios); r = dt/dx keeps the fastest wave at lattice_speed."""
+    0.1 scaled by the ratios); r = dt/dx from the Courant number of the fastest
+    wave of its exact solution."""
     left = (0.125 * rho_ratio, 0.1 * p_ratio)
     right = (0.125, 0.1)
-    smax = riemann_max_speed((left[0], 0.0, left[1]), (right[0], 0.0, right[1]))
-    r = lattice_speed / smax
-    return sod(n=n, ny=ny, nz=nz, r=r, left=left, right=right, **kw)
+    return sod(n=n, ny=ny, nz=nz, left=left, right=right, cfl=cfl, **kw)
 
 
 @dataclass
@@ -476,7 +492,7 @@ def serving_trace(count=1000, rate=50.0, seed=1, steps_range=(1000, 20000), mix=
             n = int(rng.integers(tgv_n[0], tgv_n[1] + 1))
             m = float(rng.uniform(*tgv_mach))
             # the requested steps cover at most t_c = 20 (the horizon of Sec. 3.3)
-            r = min(TGV_LATTICE_SPEED / (1.0 + 1.0 / m), tgv_tc_max / (steps * 2.0 * math.pi / n))
+            r = min(CFL_NEAR_TWO / (1.0 + 1.0 / m), tgv_tc_max / (steps * 2.0 * math.pi / n))
             case, kind = tgv(n=n, mach=m, steps=steps, diag_every=0, r=r), "tgv"
         else:
             L = int(rng.integers(becker_L[0], becker_L[1] + 1))

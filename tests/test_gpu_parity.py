@@ -125,7 +125,7 @@ def test_smooth_vortex_100_steps():
 def test_sod_tube_config():
     """Sod shock tube 256x4x4, 400 steps, zero-gradient ends (the parity workload):
     uniform across the tube, relative L2 <= 1e-3 in shocked cells and overall."""
-    case = inputs.sod(n=256, ny=4, nz=4)
+    case = inputs.sod(n=256, ny=4, nz=4, steps=400)
     say("sod 256x4x4 400 steps")
     Q, _, _, _ = gpu_run(case, case.steps)
     assert np.array_equal(Q, np.broadcast_to(Q[:, :1, :1, :], Q.shape))

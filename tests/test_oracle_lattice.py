@@ -6,7 +6,7 @@
     against the exact solution of eq. 2 linearised about rest (the reconstruction
     makes the physical viscosity and conductivity of the closure the ones seen);
     with omega < 2 the additional lattice viscosity (1/omega - 1/2) c_s^2 appears
-  * Sod tube against the exact Riemann solution (Sec. 3.2, Table 3 order of magnitude)
+  * Sod tube against the exact Riemann solution and the errors Table 3 prints (Sec. 3.2)
   * Becker shock against its closed form, converging with resolution (Sec. 3.2)
   * cell-locality: quasi-1D runs stay uniform across the tube; axis permutation
   * second-order self-convergence on a smooth vortex under acoustic scaling
@@ -129,8 +129,8 @@ def test_plane_waves_match_linear_nsf(mode):
         assert np.abs(sim - lin).max() < 5e-3 * np.abs(z0).max(), (steps, sim, lin)
 
 
-def _sod_errors(n):
-    c = inputs.sod(n=n, ny=1, nz=1)
+def _sod_errors(n, r=None):
+    c = inputs.sod(n=n, ny=1, nz=1, r=r)
     f = oracle.init(c.params, c.Q0)
     f, _ = oracle.run(c.params, f, c.steps)
     q = oracle.moments(c.params, f)[:, 0, 0, :]
@@ -157,25 +157,43 @@ def test_exact_riemann_solver():
 
 def test_sod_against_exact():
     """Sod at t = 0.2: errors of the order of Table 3, converging with N, and a
-    monotone profile with no overshoot (Sec. 3.2)."""
+    profile monotone away from the shock (Sec. 3.2).  At the paper's Courant number
+    the captured shock carries a small overshoot: at most 2% in u and a density step
+    of at most 1% of the jump (measured 1.3-1.5% and 0.6% at N = 256 and 750); the
+    rest of the profile is monotone to 1e-3 of the jump."""
     e256, rho, u = _sod_errors(256)
     e512, _, _ = _sod_errors(512)
     assert e256["rho"] < 0.04 and e256["p"] < 0.04 and e256["u"] < 0.09, e256
     for key in ("rho", "p", "u"):
         assert e512[key] < e256[key]
     assert rho.min() > 0.125 - 1e-9 and rho.max() < 1.0 + 1e-9
-    assert np.diff(rho).max() < 1e-3 * (1.0 - 0.125)
-    assert u.max() < 0.92745 * 1.005
+    x = (np.arange(256) + 0.5) / 256
+    near_shock = np.abs(x[:-1] - (0.5 + 1.7522 * 0.2)) < 8.0 / 256
+    d = np.diff(rho)
+    assert d[~near_shock].max() < 1e-3 * (1.0 - 0.125)
+    assert d[near_shock].max() < 1e-2 * (1.0 - 0.125)
+    assert u.max() < 0.92745 * 1.02
 
 
-def test_sod_golden_table3():
-    """At N = 750 the oracle lands within a factor 1.5 of Table 3 (the paper runs a
-    different Courant number, so this is an order-of-magnitude check)."""
+@pytest.mark.parametrize("n", [750, 1500, 3000])
+def test_sod_golden_table3(n):
+    """Table 3 (Sec. 3.2) at the paper's own Courant number: 0.35 read as the Courant
+    number of the fastest characteristic of the exact solution, lambda_max dt/dx
+    (Table 1).  Every error lands within 12% of the printed value (measured: within
+    7% at N = 750 and 1500, 10% at 3000, 3% at 6000)."""
     g = json.load(open(os.path.join(GOLDEN, "sod_table3.json")))
-    row = [r for r in g["rows"] if r["N"] == 750][0]
-    e, _, _ = _sod_errors(750)
+    row = [r for r in g["rows"] if r["N"] == n][0]
+    e, _, _ = _sod_errors(n)
     for key in ("rho", "p", "u"):
-        assert row[key] / 1.5 < e[key] < row[key] * 1.5, (key, e[key], row[key])
+        assert abs(e[key] / row[key] - 1.0) < 0.12, (key, e[key], row[key])
+
+
+def test_sod_literal_courant_reading_diverges():
+    """The literal reading dt/dx = 0.35 moves the post-shock characteristic 0.77 cells
+    per step, beyond the D3Q7 sound speed 1/2: the run does not stay finite."""
+    with np.errstate(invalid="ignore", over="ignore"):
+        e, rho, _ = _sod_errors(750, r=0.35)
+    assert not np.isfinite(rho).all()
 
 
 def _becker_err(cpf, mach=2.0, steps=2000):
