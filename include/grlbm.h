@@ -212,6 +212,27 @@ lbm_status lbm_get_step(lbm_ctx* ctx, int64_t* step);
 /* Release the context (waits for its stream first).  NULL is a no-op. */
 lbm_status lbm_destroy(lbm_ctx* ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lbm_step without a
+ * context and without any allocation.  Advances the caller's populations F_dev
+ * (device, FP32 storage, the layout and lbm_state_bytes(p) of a context with the
+ * same params, holding the state after `step` completed steps, e.g. the buffer of
+ * an lbm_create_in context) by n steps with the kernels and the default launch
+ * shape of lbm_step, asynchronously on hip_stream (a hipStream_t, NULL = the null
+ * stream).  With diag_every > 0 each step t in [step, step + n) with
+ * t % diag_every == 0 writes one record of 9 floats to rec_dev (device, caller-
+ * owned, rec_max records): E_k, eps_s, eps_d, the five dtotal and the non-finite
+ * count, as lbm_diag holds them.  The per-block partials of those reductions live
+ * in one fixed device array of the library per GPU (2^18 blocks x 9 floats, 9 MiB,
+ * held until the process ends); every call on a GPU shares it and it keeps the last
+ * call's contents, so calls that overlap on one GPU race.  EINVAL: invalid params,
+ * FP16 storage, a NULL or misaligned buffer, negative step, n or diag_every, too
+ * few records in rec_max, or a grid whose launches need more than 2^18 partial
+ * blocks (more than about 67 M cells) when diag_every > 0.  Calls no hipMalloc or
+ * hipFree. */
+lbm_status lbm_step_noalloc(const lbm_params* p, void* F_dev, int64_t step, int64_t n, int32_t diag_every,
+                            float* rec_dev, int32_t rec_max, void* hip_stream);
+
 /* ------------------------------------------------------------------ batches
  * Many independent instances (different sizes, boundaries, parameters, storage
  * types and start times) advanced together: one persistent kernel per (collision,

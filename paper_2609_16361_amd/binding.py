@@ -113,6 +113,8 @@ SIGNATURES = {
                                       ctypes.c_double, _vp, _vp]),
     "lbm_get_step": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "lbm_destroy": (ctypes.c_int, [_vp]),
+    "lbm_step_noalloc": (ctypes.c_int, [_P(lbm_params), _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                        _vp, ctypes.c_int32, _vp]),
     "lbm_bw_probe": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, _P(ctypes.c_double)]),
     "lbm_last_error": (ctypes.c_char_p, []),
     "lbm_batch_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -277,6 +279,14 @@ def lbm_get_step(ctx: int) -> int:
 
 def lbm_destroy(ctx: int) -> None:
     _check(load().lbm_destroy(ctx), "lbm_destroy")
+
+
+def lbm_step_noalloc(params: lbm_params, F_dev: int, step: int, n: int, diag_every: int = 0,
+                     rec_dev: int | None = None, rec_max: int = 0, stream: int | None = None) -> None:
+    """F_dev, rec_dev: device addresses (e.g. tensor.data_ptr()); rec_dev receives
+    9 floats per diagnostic step."""
+    _check(load().lbm_step_noalloc(ctypes.byref(params), F_dev, int(step), int(n), int(diag_every), rec_dev,
+                                   int(rec_max), stream), "lbm_step_noalloc")
 
 
 def lbm_bw_probe(nbytes: int, iters: int = 10) -> float:

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -695,6 +696,103 @@ done:
   if (a) (void)hipFree(a);
   if (b) (void)hipFree(b);
   return st;
+}
+
+}  // extern "C"
+
+// Device memory for lbm_step_noalloc: the per-block diagnostic partials of one
+// launch (kDiagVals floats per block), for grids whose launches have at most
+// kNoAllocBlocks blocks.  Every launch writes each partial that its finalize then
+// reads, so nothing here has to start at zero.  Each GPU holds its own copy at its
+// own address, found once per device with hipGetSymbolAddress; host code uses only
+// that address (the array's name is a host-side stand-in).
+constexpr int64_t kNoAllocBlocks = int64_t(1) << 18;
+static __device__ __align__(256) float scratch[kNoAllocBlocks * 9];
+
+namespace {
+
+static_assert(kDiagVals == 9, "scratch holds 9 diagnostic values per block");
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+lbm_status scratch_address(int dev, float** out) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(LBM_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+// Steps t in [step, step + n) with t % every == 0.
+int64_t diag_count(int64_t step, int64_t n, int64_t every) {
+  if (every <= 0 || n <= 0) return 0;
+  const int64_t first = (step + every - 1) / every * every;
+  return first < step + n ? (step + n - 1 - first) / every + 1 : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_step_noalloc(const lbm_params* p, void* F_dev, int64_t step, int64_t n, int32_t diag_every,
+                            float* rec_dev, int32_t rec_max, void* hip_stream) {
+  lbm_status st = validate(p);
+  if (st != LBM_OK) return st;
+  if (!F_dev) return fail(LBM_EINVAL, "population buffer is NULL");
+  if (((uintptr_t)F_dev) % 256 != 0) return fail(LBM_EINVAL, "population buffer is not 256-byte aligned");
+  if (p->storage != LBM_STORE_F32)
+    return fail(LBM_EINVAL, "lbm_step_noalloc takes FP32 storage only (FP16 scales are set at initialisation)");
+  if (step < 0 || n < 0 || diag_every < 0) return fail(LBM_EINVAL, "step, n and diag_every must be >= 0");
+  const int64_t records = diag_count(step, n, diag_every);
+  if (records > 0 && (!rec_dev || rec_max < records))
+    return fail(LBM_EINVAL, "%lld diagnostic records need room in rec_dev (rec_max = %d)", (long long)records,
+                rec_max);
+  grlbm::StepLaunch L;
+  L.F = F_dev;
+  L.g = make_grid(p);
+  L.c = make_coll(p);
+  L.block = 256;  // the launch shape of a new context
+  L.coll = p->collision;
+  L.f16 = false;
+  L.nt = true;
+  L.lds = lds_for_blocks_per_cu(kDefaultBlocksPerCuF32);
+  L.odd_lds = true;
+  L.src = nullptr;
+  L.partials = nullptr;
+  float* partials = nullptr;
+  if (records > 0) {
+    const int64_t nb = std::max(grlbm::step_blocks(L.g, L.block), grlbm::odd_tiles(L.g, false).blocks);
+    if (nb > kNoAllocBlocks)
+      return fail(LBM_EINVAL, "the grid's launches need %lld diagnostic partial blocks; the fixed scratch holds %lld",
+                  (long long)nb, (long long)kNoAllocBlocks);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(LBM_EDEVICE, "no HIP device");
+    st = scratch_address(dev, &partials);
+    if (st != LBM_OK) return st;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  int64_t r = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t t = step + k;
+    const bool diag = diag_every > 0 && (t % diag_every) == 0;
+    L.odd = (t & 1) != 0;
+    L.diag = diag;
+    L.skey = grlbm::step_key(t);
+    L.partials = diag ? partials : nullptr;
+    HIP_TRY(grlbm::launch_step(L, s));
+    if (diag) {
+      HIP_TRY(grlbm::launch_finalize(partials, grlbm::launch_blocks(L), rec_dev + r * kDiagVals, s));
+      ++r;
+    }
+  }
+  return LBM_OK;
 }
 
 const char* lbm_last_error(void) { return grlbm::g_err.c_str(); }
