@@ -78,8 +78,9 @@ typedef struct {
   double rho_ref, E_ref;       /* reference state of the equilibrium shift              */
 } lbm_params;
 
-/* One diagnostic record, reduced over all cells at the start of step `step` (the
- * state after `step` completed steps): volume sums of the kinetic energy density
+/* One diagnostic record (the channels of Sec. 3.3), reduced over all cells at the
+ * start of step `step` (the state after `step` completed steps): volume sums of the
+ * kinetic energy density
  * rho|u|^2/2, the solenoidal dissipation mu|curl u|^2 and the dilatational
  * dissipation (4/3) mu (div u)^2 (velocity gradient from the reconstruction), the
  * totals of the five conserved fields minus N Q_ref, and the number of cells whose
@@ -112,10 +113,20 @@ lbm_status lbm_create(const lbm_params* p, void* hip_stream, lbm_ctx** out);
 lbm_status lbm_create_in(const lbm_params* p, void* dev_buf, size_t bytes, void* hip_stream,
                          lbm_ctx** out);
 
-/* Set the state to the equilibrium of Q with the advective flux only (no
- * non-equilibrium part) and reset the step counter to 0.  Q: host array
+/* Set the state from the conserved fields Q and reset the step counter to 0.  The
+ * paper states no initialisation; the populations get zeroth moment Q, the
+ * equilibrium second moment and the first moment J_k = Phi_k - (c_s^2/omega_k)
+ * grad Q_k that the update holds a smooth field at to first order (the fixed point
+ * of the relaxation of the first moment followed by streaming), with grad Q from
+ * central differences of Q (periodic wrap; beyond a zero-gradient face the cell
+ * itself) and Phi the flux of eq. 2 with the Newtonian stress and Fourier flux of
+ * that gradient.  The reconstruction of eq. 4 returns that gradient at step 0, and
+ * no step-to-step oscillation of the non-equilibrium is started (omega -> 2 would
+ * leave it undamped).  A uniform state starts at its equilibrium.  Q: host array
  * [5][nz][ny][nx] of doubles, lattice units, field order (rho, rho u_x, rho u_y,
- * rho u_z, E).  Synchronises the stream before returning. */
+ * rho u_z, E).  EINVAL (state unchanged) if a value is not finite or the density
+ * or the pressure (gamma - 1)(E - |rho u|^2 / (2 rho)) of a cell is not positive.
+ * Synchronises the stream before returning. */
 lbm_status lbm_init_fields(lbm_ctx* ctx, const double* Q);
 
 /* Same, with Q already in device memory (float64, same layout); asynchronous for
@@ -274,8 +285,9 @@ lbm_status lbm_batch_create(size_t arena_bytes, int32_t max_instances, int32_t m
                             int32_t graph_steps, void* hip_stream, lbm_batch** out);
 
 /* Add an instance (params as for lbm_create, validated the same way) initialised
- * like lbm_init_fields from the host array Q [5][nz][ny][nx], to make `steps`
- * steps.  *id receives its handle.  ENOMEM when the arena has no free run large
+ * like lbm_init_fields from the host array Q [5][nz][ny][nx] (checked the same
+ * way: EINVAL for a non-finite value or a cell whose density or pressure is not
+ * positive), to make `steps` steps.  *id receives its handle.  ENOMEM when the arena has no free run large
  * enough, the descriptor table is full or its tiles exceed max_tiles. */
 lbm_status lbm_batch_add(lbm_batch* b, const lbm_params* p, const double* Q, int64_t steps,
                          int32_t* id);

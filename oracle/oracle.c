@@ -23,6 +23,8 @@
  *   8. Newtonian stress and Fourier flux (eq. 2), full flux Phi in the equilibrium
  *   9. regularized collision with reduced rate omega_h, or BGK (Sec. 2.2, 2.5)
  *  10. exact on-lattice push streaming into a second buffer
+ * Initial state (ora_init): populations with the first-order non-equilibrium first
+ * moment of the initial fields' central-difference gradients (see ora_init).
  * With a source S of eq. 1 (ora_step_src) the post-collision populations gain
  * w_i S_k before streaming (the collision of Algorithm 1).  ora_mms_source writes the
  * source of the manufactured solution of Sec. 3.1 (eq. 8), derived by hand from
@@ -358,18 +360,60 @@ static int ora_shift(int x, int dx, int n, int bc) {
   return -1;
 }
 
-/* Initial populations: equilibrium of Q with the advective flux only (no
- * non-equilibrium part).  Q[5][N] -> f[35][N]. */
+/* coordinate of the neighbour along an axis for a central difference: periodic
+ * wrap, or the cell itself beyond a zero-gradient face (the ghost copy) */
+static int ora_fd_nb(int x, int d, int n, int bc) {
+  int y = x + d;
+  if (y >= 0 && y < n) return y;
+  if (bc == 0) return (y % n + n) % n;
+  return x;
+}
+
+/* Initial populations (the paper states no initialisation): the populations whose
+ * first moment is the one the update holds a smooth field at to first order,
+ *   J_k = Phi_k - (c_s^2 / omega_k) grad Q_k,   Phi = Phi_adv + M grad Q
+ * (the non-equilibrium first moment of a collide-and-stream cycle: with
+ * J* = Phi + (1 - omega)(J - Phi) and streaming J = J* - c_s^2 grad Q), with grad Q
+ * from central differences of the initial fields (periodic wrap, or the cell itself
+ * as the ghost beyond a zero-gradient face) and the second moment at equilibrium:
+ * f_i = w_i (Q + c_i . J / c_s^2).  The reconstruction of eq. 4 then returns that
+ * grad Q at step 0, and no odd-even start-up oscillation of the non-equilibrium is
+ * excited (at omega -> 2 it would not decay).  A uniform state gets f = f_eq.
+ * Q[5][N] -> f[35][N]. */
 void ora_init(const ora_params* P, const double* Q, double* f) {
+  const int nx = P->nx, ny = P->ny, nz = P->nz;
   const int64_t N = ora_cells(P);
-  for (int64_t n = 0; n < N; ++n) {
-    double q[5], u[3], rf, k2, p, T, F[5][3];
-    for (int k = 0; k < 5; ++k) q[k] = Q[k * N + n];
-    ora_primitives(P, q, &rf, u, &k2, &p, &T);
-    ora_flux_adv(q, u, p, F);
-    for (int k = 0; k < 5; ++k)
-      for (int i = 0; i < 7; ++i) f[(7 * k + i) * N + n] = ora_feq(i, q[k], F[k]);
-  }
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t n = x + (int64_t)nx * (y + (int64_t)ny * z);
+        double q[5], u[3], rf, k2, p, T, F[5][3], G[5][3], M[15][15], J[5][3];
+        for (int k = 0; k < 5; ++k) q[k] = Q[k * N + n];
+        ora_primitives(P, q, &rf, u, &k2, &p, &T);
+        ora_flux_adv(q, u, p, F);
+        /* central differences of the initial fields */
+        const int64_t xm = ora_fd_nb(x, -1, nx, P->bc[0]) + (int64_t)nx * (y + (int64_t)ny * z);
+        const int64_t xp = ora_fd_nb(x, 1, nx, P->bc[0]) + (int64_t)nx * (y + (int64_t)ny * z);
+        const int64_t ym = x + (int64_t)nx * (ora_fd_nb(y, -1, ny, P->bc[1]) + (int64_t)ny * z);
+        const int64_t yp = x + (int64_t)nx * (ora_fd_nb(y, 1, ny, P->bc[1]) + (int64_t)ny * z);
+        const int64_t zm = x + (int64_t)nx * (y + (int64_t)ny * ora_fd_nb(z, -1, nz, P->bc[2]));
+        const int64_t zp = x + (int64_t)nx * (y + (int64_t)ny * ora_fd_nb(z, 1, nz, P->bc[2]));
+        for (int k = 0; k < 5; ++k) {
+          G[k][0] = 0.5 * (Q[k * N + xp] - Q[k * N + xm]);
+          G[k][1] = 0.5 * (Q[k * N + yp] - Q[k * N + ym]);
+          G[k][2] = 0.5 * (Q[k * N + zp] - Q[k * N + zm]);
+        }
+        const double ratio = ora_mu_ratio(P, T);
+        ora_assemble_M(P, rf, u, T, P->mu_ref * ratio, P->kappa_ref * ratio, M);
+        for (int r = 0; r < 15; ++r) {
+          double d = 0.0;
+          for (int cc = 0; cc < 15; ++cc) d += M[r][cc] * G[cc / 3][cc % 3];
+          const int k = r / 3, c = r % 3;
+          J[k][c] = F[k][c] + d - ORA_CS2 / P->omega[k] * G[k][c];
+        }
+        for (int k = 0; k < 5; ++k)
+          for (int i = 0; i < 7; ++i) f[(7 * k + i) * N + n] = ora_feq(i, q[k], J[k]);
+      }
 }
 
 /* Zeroth moments of every field: f[35][N] -> Q[5][N]. */

@@ -85,6 +85,20 @@ lbm_status validate(const lbm_params* p) {
   return LBM_OK;
 }
 
+lbm_status check_fields(const lbm_params* p, const double* Q) {
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  const double g1 = p->gamma - 1.0;
+  for (int64_t n = 0; n < N; ++n) {
+    const double rho = Q[n], m0 = Q[N + n], m1 = Q[2 * N + n], m2 = Q[3 * N + n], E = Q[4 * N + n];
+    if (!(std::isfinite(rho) && std::isfinite(m0) && std::isfinite(m1) && std::isfinite(m2) && std::isfinite(E)))
+      return fail(LBM_EINVAL, "initial fields are not finite at cell %lld", (long long)n);
+    if (!(rho > 0.0)) return fail(LBM_EINVAL, "initial density %g at cell %lld is not positive", rho, (long long)n);
+    const double pr = g1 * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho);
+    if (!(pr > 0.0)) return fail(LBM_EINVAL, "initial pressure %g at cell %lld is not positive", pr, (long long)n);
+  }
+  return LBM_OK;
+}
+
 int64_t slot_stride(const lbm_params* p) {
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
   const int64_t el = p->storage == LBM_STORE_F16 ? 2 : 4;
@@ -150,12 +164,29 @@ static lbm_status read_maxabs(Coll& c, unsigned* d, hipStream_t s) {
   return LBM_OK;
 }
 
-lbm_status scales_from_fields(Coll& c, const Grid& g, const double* Q_dev, int64_t N, hipStream_t s) {
+InitCoef make_init_coef(const lbm_params* p) {
+  InitCoef ic;
+  ic.gm1 = p->gamma - 1.0;
+  ic.mu_ref = p->mu_ref;
+  ic.kappa_ref = p->kappa_ref;
+  ic.T_ref = p->T_ref;
+  ic.T_S = p->T_S;
+  ic.rho_min = p->rho_min;
+  ic.p_min = p->p_min;
+  ic.rho_ref = p->rho_ref;
+  ic.E_ref = p->E_ref;
+  for (int k = 0; k < 5; ++k) ic.inv_omega[k] = 1.0 / p->omega[k];
+  ic.sutherland = p->mu_law == LBM_MU_SUTHERLAND ? 1 : 0;
+  return ic;
+}
+
+lbm_status scales_from_fields(Coll& c, const Grid& g, const InitCoef& ic, const double* Q_dev, int64_t N,
+                              hipStream_t s) {
   unsigned* d = nullptr;
   if (hipMalloc((void**)&d, 5 * sizeof(unsigned)) != hipSuccess) return fail(LBM_ENOMEM, "hipMalloc failed");
   lbm_status st = LBM_OK;
   if (hipMemsetAsync(d, 0, 5 * sizeof(unsigned), s) != hipSuccess ||
-      launch_init_maxabs(g, c, Q_dev, N, d, s) != hipSuccess)
+      launch_init_maxabs(g, c, ic, Q_dev, N, d, s) != hipSuccess)
     st = fail(LBM_EDEVICE, "storage-scale reduction failed");
   if (st == LBM_OK) st = read_maxabs(c, d, s);
   (void)hipFree(d);
@@ -476,10 +507,11 @@ lbm_status lbm_set_source(lbm_ctx* c, const float* S_dev) {
 lbm_status lbm_init_fields_device(lbm_ctx* c, const double* Q_dev) {
   if (!c || !Q_dev) return fail(LBM_EINVAL, "ctx or Q is NULL");
   if (c->p.storage == LBM_STORE_F16) {
-    lbm_status st = grlbm::scales_from_fields(c->c, c->g, Q_dev, c->N, c->stream);
+    lbm_status st = grlbm::scales_from_fields(c->c, c->g, grlbm::make_init_coef(&c->p), Q_dev, c->N, c->stream);
     if (st != LBM_OK) return st;
   }
-  HIP_TRY(grlbm::launch_init(c->F, c->p.storage == LBM_STORE_F16, c->g, c->c, Q_dev, c->N, c->stream));
+  HIP_TRY(grlbm::launch_init(c->F, c->p.storage == LBM_STORE_F16, c->g, c->c, grlbm::make_init_coef(&c->p), Q_dev,
+                             c->N, c->stream));
   c->step = 0;
   c->ready = true;
   c->ring_used = 0;
@@ -490,6 +522,8 @@ lbm_status lbm_init_fields_device(lbm_ctx* c, const double* Q_dev) {
 
 lbm_status lbm_init_fields(lbm_ctx* c, const double* Q) {
   if (!c || !Q) return fail(LBM_EINVAL, "ctx or Q is NULL");
+  lbm_status st0 = grlbm::check_fields(&c->p, Q);
+  if (st0 != LBM_OK) return st0;
   double* d = nullptr;
   lbm_status st = dev_alloc(&d, (size_t)5 * c->N, "initial fields");
   if (st != LBM_OK) return st;

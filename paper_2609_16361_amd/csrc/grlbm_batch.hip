@@ -477,6 +477,8 @@ lbm_status lbm_batch_add(lbm_batch* b, const lbm_params* p, const double* Q, int
   if (steps < 0) return fail(LBM_EINVAL, "steps < 0");
   lbm_status st = grlbm::validate(p);
   if (st != LBM_OK) return st;
+  st = grlbm::check_fields(p, Q);
+  if (st != LBM_OK) return st;
   int32_t slot = -1;
   for (int32_t i = 0; i < (int32_t)b->insts.size(); ++i)
     if (!b->insts[i].live) {
@@ -520,7 +522,7 @@ lbm_status lbm_batch_add(lbm_batch* b, const lbm_params* p, const double* Q, int
   }
   hipError_t e = hipMemcpyAsync(dq, Q, sizeof(double) * 5 * (size_t)N, hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess && p->storage == LBM_STORE_F16) {
-    st = grlbm::scales_from_fields(h.d.c, h.d.g, dq, N, b->stream);
+    st = grlbm::scales_from_fields(h.d.c, h.d.g, grlbm::make_init_coef(p), dq, N, b->stream);
     if (st != LBM_OK) {
       (void)hipFree(dq);
       arena_free(b, off, bytes);
@@ -528,7 +530,8 @@ lbm_status lbm_batch_add(lbm_batch* b, const lbm_params* p, const double* Q, int
     }
   }
   if (e == hipSuccess)
-    e = grlbm::launch_init(b->arena + off, p->storage == LBM_STORE_F16, h.d.g, h.d.c, dq, N, b->stream);
+    e = grlbm::launch_init(b->arena + off, p->storage == LBM_STORE_F16, h.d.g, h.d.c, grlbm::make_init_coef(p), dq,
+                           N, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   (void)hipFree(dq);
   if (e != hipSuccess) {

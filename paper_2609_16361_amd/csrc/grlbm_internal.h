@@ -18,10 +18,23 @@ namespace grlbm {
 
 lbm_status fail(lbm_status st, const char* fmt, ...);
 lbm_status validate(const lbm_params* p);
+// Initial conserved fields Q[5][N] (host) describe a physical state: every value
+// finite, density and pressure positive in every cell; EINVAL names the first cell
+// that is not.
+lbm_status check_fields(const lbm_params* p, const double* Q);
 int64_t slot_stride(const lbm_params* p);
 size_t state_bytes(const lbm_params* p);
 Coll make_coll(const lbm_params* p);
 Grid make_grid(const lbm_params* p);
+
+// Coefficients of the initial state (k_init), FP64: it is computed once per solve.
+struct InitCoef {
+  double gm1, mu_ref, kappa_ref, T_ref, T_S;
+  double rho_min, p_min, rho_ref, E_ref;
+  double inv_omega[5];
+  int32_t sutherland;
+};
+InitCoef make_init_coef(const lbm_params* p);
 
 struct StepLaunch {
   void* F;           // population buffer
@@ -71,14 +84,14 @@ int64_t pair_blocks(const StepLaunch& L);    // its blocks
 bool odd_pairs(const StepLaunch& L);         // the odd step runs k_step_odd_row_pairs
 int odd_pair_lds(const Grid& g);             // its dynamic LDS bytes per block
 hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, hipStream_t s);
-hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const double* Q, int64_t N,
-                       hipStream_t s);
+hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const InitCoef& ic, const double* Q,
+                       int64_t N, hipStream_t s);
 hipError_t launch_gather(const void* F, bool f16, const Grid& g, const Coll& c, int64_t N, bool odd,
                          int mode, float* out_f, double* out_q, hipStream_t s);
 hipError_t launch_scatter(void* F, bool f16, const Grid& g, const Coll& c, int64_t N, bool odd,
                           const float* in_f, hipStream_t s);
-hipError_t launch_init_maxabs(const Grid& g, const Coll& c, const double* Q, int64_t N, unsigned* maxabs,
-                              hipStream_t s);
+hipError_t launch_init_maxabs(const Grid& g, const Coll& c, const InitCoef& ic, const double* Q, int64_t N,
+                              unsigned* maxabs, hipStream_t s);
 hipError_t launch_maxabs_pops(const float* f, int64_t N, unsigned* maxabs, hipStream_t s);
 // FP16 storage: pick power-of-two scales so that each field's largest initial |g|
 // maps into [32, 64): 1024x headroom below the FP16 maximum for populations that
@@ -89,7 +102,8 @@ hipError_t launch_maxabs_pops(const float* f, int64_t N, unsigned* maxabs, hipSt
 void set_storage_scales(Coll& c, const unsigned maxabs_bits[5]);
 // Scales from the initial fields Q (device) or from canonical populations f
 // (device); synchronises the stream to read the maxima back.
-lbm_status scales_from_fields(Coll& c, const Grid& g, const double* Q_dev, int64_t N, hipStream_t s);
+lbm_status scales_from_fields(Coll& c, const Grid& g, const InitCoef& ic, const double* Q_dev, int64_t N,
+                              hipStream_t s);
 lbm_status scales_from_pops(Coll& c, const float* f_dev, int64_t N, hipStream_t s);
 hipError_t launch_copy(const void* a, void* b, int64_t bytes, hipStream_t s);
 

@@ -9,7 +9,7 @@
 //   k_step_even_pairs, k_step_odd_row_pairs  FP16 even and odd half steps with
 //               two consecutive cells per lane (4-byte accesses) on large grids
 //   k_finalize  deterministic reduction of the per-block partials into one record
-//   k_init      equilibrium populations from the conserved fields
+//   k_init      initial populations from the conserved fields (first-order start)
 //   k_gather    parity-aware readout: canonical populations or conserved moments
 //   k_scatter   parity-aware write of canonical populations (checkpoint restore)
 //   k_copy      streaming copy used to measure achievable HBM bandwidth
@@ -206,36 +206,91 @@ __device__ __forceinline__ void field_max(unsigned* maxabs, int k, float v) {
   atomicMax(maxabs + k, __float_as_uint(fabsf(v)));
 }
 
-// Equilibrium of Q with the advective flux: g_i = w_i (Q - Q_ref + 4 c_i . Phi_adv),
-// stored times the field's storage scale.  With maxabs set, nothing is stored and
-// the largest |g| of each field is reduced instead (used to pick the FP16 scales).
+// Neighbour index along one axis for a central difference: periodic wrap, or the
+// cell itself beyond a zero-gradient face (the ghost holds a copy of the cell).
+__device__ __forceinline__ int64_t fd_neighbour(int64_t n, int x, int d, int len, int zg, int64_t stride) {
+  int xx = x + d;
+  if (xx < 0 || xx >= len) xx = zg ? x : (xx + len) % len;
+  return n + (int64_t)(xx - x) * stride;
+}
+
+// Initial populations (the paper gives no initialisation): what a smooth field holds
+// between two steps of the update, to first order.  Zeroth moment Q, second moment
+// at equilibrium, first moment
+//   J_k = Phi_adv,k + Phi_diff,k - (c_s^2 / omega_k) grad Q_k,
+// the fixed point of the relaxation J* = Phi + (1 - omega)(J - Phi) followed by
+// streaming, J = J* - c_s^2 grad Q.  grad Q comes from central differences of the
+// initial fields, Phi_diff = (0, -tau, -tau u + q) from the Newtonian stress and
+// Fourier flux of eq. 2 at that gradient (chain rule to grad u and grad T).  Without
+// the non-equilibrium part the first streaming leaves J - Phi = -c_s^2 grad Q, omega
+// times too large, and the difference oscillates from step to step undamped as
+// omega -> 2.  Computed in FP64, stored as g_i = w_i (Q - Q_ref + 4 c_i . J) times
+// the field's storage scale.  With maxabs set, nothing is stored and the largest |g|
+// of each field is reduced instead (used to pick the FP16 scales).
 template <typename T>
-__global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
+__global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c, InitCoef ic,
                                                const double* __restrict__ Q, int64_t N,
                                                unsigned* __restrict__ maxabs) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  const float rho = (float)Q[n];
-  const float m[3] = {(float)Q[N + n], (float)Q[2 * N + n], (float)Q[3 * N + n]};
-  const float E = (float)Q[4 * N + n];
-  const float dq[5] = {(float)(Q[n] - (double)c.rho_ref), m[0], m[1], m[2],
-                       (float)(Q[4 * N + n] - (double)c.E_ref)};
-  const float rf = fmaxf(rho, c.rho_min);
-  const float ir = 1.0f / rf;
-  const float u[3] = {m[0] * ir, m[1] * ir, m[2] * ir};
-  const float k2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  const float p = fmaxf(c.gm1 * (E - 0.5f * rf * k2), c.p_min);
-  float Phi[5][3];
-  for (int cc = 0; cc < 3; ++cc) {
-    Phi[0][cc] = m[cc];
-    for (int j = 0; j < 3; ++j) Phi[1 + j][cc] = m[j] * u[cc] + (j == cc ? p : 0.0f);
-    Phi[4][cc] = (E + p) * u[cc];
-  }
+  const int64_t row = n / g.nx;
+  const int x = (int)(n - row * g.nx);
+  const int y = (int)(row % g.ny);
+  const int z = (int)(row / g.ny);
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  const int64_t xm = fd_neighbour(n, x, -1, g.nx, g.zg_x, 1), xp = fd_neighbour(n, x, 1, g.nx, g.zg_x, 1);
+  const int64_t ym = fd_neighbour(n, y, -1, g.ny, g.zg_y, g.nx), yp = fd_neighbour(n, y, 1, g.ny, g.zg_y, g.nx);
+  const int64_t zm = fd_neighbour(n, z, -1, g.nz, g.zg_z, plane), zp = fd_neighbour(n, z, 1, g.nz, g.zg_z, plane);
+  double q[5], G[5][3];
   for (int k = 0; k < 5; ++k) {
-    const float q8 = 0.125f * dq[k];
-    const float v[7] = {0.25f * dq[k],         q8 + 0.5f * Phi[k][0], q8 - 0.5f * Phi[k][0],
-                        q8 + 0.5f * Phi[k][1], q8 - 0.5f * Phi[k][1], q8 + 0.5f * Phi[k][2],
-                        q8 - 0.5f * Phi[k][2]};
+    const double* Qk = Q + k * N;
+    q[k] = Qk[n];
+    G[k][0] = 0.5 * (Qk[xp] - Qk[xm]);
+    G[k][1] = 0.5 * (Qk[yp] - Qk[ym]);
+    G[k][2] = 0.5 * (Qk[zp] - Qk[zm]);
+  }
+  const double rf = fmax(q[0], ic.rho_min);
+  const double u[3] = {q[1] / rf, q[2] / rf, q[3] / rf};
+  const double k2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const double p = fmax(ic.gm1 * (q[4] - 0.5 * rf * k2), ic.p_min);
+  const double Tc = p / rf;
+  double ratio = 1.0;
+  if (ic.sutherland) {
+    const double t = Tc / ic.T_ref;
+    ratio = (1.0 + ic.T_S) * t * sqrt(t) / (t + ic.T_S);
+  }
+  const double mu = ic.mu_ref * ratio, kap = ic.kappa_ref * ratio;
+  // grad u = (grad(rho u) - u (x) grad rho)/rho and the chain rule for grad T
+  double du[3][3], dT[3];
+  for (int cc = 0; cc < 3; ++cc) {
+    double um = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      du[j][cc] = (G[1 + j][cc] - u[j] * G[0][cc]) / rf;
+      um += u[j] * G[1 + j][cc];
+    }
+    dT[cc] = ic.gm1 / rf * (G[4][cc] - um) + (0.5 * ic.gm1 * k2 - Tc) / rf * G[0][cc];
+  }
+  const double theta = du[0][0] + du[1][1] + du[2][2];
+  double tau[3][3];
+  for (int j = 0; j < 3; ++j)
+    for (int cc = 0; cc < 3; ++cc)
+      tau[j][cc] = mu * (du[j][cc] + du[cc][j] - (j == cc ? 2.0 / 3.0 * theta : 0.0));
+  double J[5][3];
+  for (int cc = 0; cc < 3; ++cc) {
+    J[0][cc] = q[1 + cc] - 0.25 * ic.inv_omega[0] * G[0][cc];
+    for (int j = 0; j < 3; ++j)
+      J[1 + j][cc] = q[1 + j] * u[cc] + (j == cc ? p : 0.0) - tau[j][cc] -
+                     0.25 * ic.inv_omega[1 + j] * G[1 + j][cc];
+    const double tu = tau[cc][0] * u[0] + tau[cc][1] * u[1] + tau[cc][2] * u[2];
+    J[4][cc] = (q[4] + p) * u[cc] - tu - kap * dT[cc] - 0.25 * ic.inv_omega[4] * G[4][cc];
+  }
+  const double ref[5] = {ic.rho_ref, 0.0, 0.0, 0.0, ic.E_ref};
+  for (int k = 0; k < 5; ++k) {
+    const double dq = q[k] - ref[k];
+    const double q8 = 0.125 * dq;
+    const float v[7] = {(float)(0.25 * dq),           (float)(q8 + 0.5 * J[k][0]), (float)(q8 - 0.5 * J[k][0]),
+                        (float)(q8 + 0.5 * J[k][1]), (float)(q8 - 0.5 * J[k][1]), (float)(q8 + 0.5 * J[k][2]),
+                        (float)(q8 - 0.5 * J[k][2])};
     if (maxabs) {
       float m = 0.0f;
       for (int i = 0; i < kQ; ++i) m = fmaxf(m, fabsf(v[i]));
@@ -459,20 +514,20 @@ hipError_t launch_finalize(const float* partials, int64_t nblocks, float* rec, h
   return hipGetLastError();
 }
 
-hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const double* Q, int64_t N,
-                       hipStream_t s) {
+hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const InitCoef& ic, const double* Q,
+                       int64_t N, hipStream_t s) {
   const unsigned blocks = (unsigned)((N + 255) / 256);
   if (f16)
-    hipLaunchKernelGGL(k_init<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, c, Q, N, nullptr);
+    hipLaunchKernelGGL(k_init<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, c, ic, Q, N, nullptr);
   else
-    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, c, Q, N, nullptr);
+    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, c, ic, Q, N, nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_init_maxabs(const Grid& g, const Coll& c, const double* Q, int64_t N, unsigned* maxabs,
-                              hipStream_t s) {
+hipError_t launch_init_maxabs(const Grid& g, const Coll& c, const InitCoef& ic, const double* Q, int64_t N,
+                              unsigned* maxabs, hipStream_t s) {
   const unsigned blocks = (unsigned)((N + 255) / 256);
-  hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, nullptr, g, c, Q, N, maxabs);
+  hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, nullptr, g, c, ic, Q, N, maxabs);
   return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ def test_smooth_vortex_100_steps():
     for r, ro in zip(d, dor):
         assert r["nonfinite"] == 0
         assert r["Ek"] == pytest.approx(ro[0], rel=2e-5)
-        if r["step"] > 0:   # gradients are zero at the equilibrium start
+        if r["step"] > 0:   # at step 0 the gradients are the start's central differences
             assert r["eps_s"] == pytest.approx(ro[1], rel=2e-4)
             assert r["eps_d"] == pytest.approx(ro[2], rel=2e-3, abs=1e-6 * ro[1])
         N = case.cells
@@ -120,6 +120,35 @@ def test_smooth_vortex_100_steps():
         for k in range(5):
             tot = ro[3 + k] - N * qref[k]
             assert abs(r["dtotal"][k] - tot) <= 1e-5 * (abs(ro[3 + k]) + 1e-3 * N), k
+
+
+def test_vortex_at_the_256_operating_point():
+    """The benchmark's 256^3 recipe (omega = 1.9999887 from f_mu = 0.001, the time
+    step, Sutherland viscosity, sensor g = 40, J_min = 1e-2, omega_min = 1.987) and
+    its launch shape (256-cell rows: one block per row in the odd step, 256-thread
+    blocks capped at 4 per CU in the even step, nontemporal access) on a periodic
+    256 x 256 x 4 slab holding the z = 0 plane of the 256^3 field in every plane
+    (smooth across every wrap): every field within 2e-5 relative L2 of the FP64
+    oracle after 100 steps, E_k within 2e-5 and eps_s, eps_d within 2e-4 and 2e-3 of
+    the largest record in their series, at steps 0, 25, 50 and 75 (both parities)."""
+    case = inputs.tgv(n=256, dims=(256, 256, 4), z_extruded=True, steps=100, diag_every=25)
+    say("tgv 256-recipe slab 256x256x4, 100 steps")
+    Q, _, d, status = gpu_run(case, 100, diag_every=25)
+    assert status == binding.LBM_OK
+    f, dor = ora_run(case, 100, diag_every=25)
+    Qo = oracle.moments(case.params, f)
+    sc = field_scales(Qo, case.params)
+    for k in range(5):
+        e = rel_l2(Q[k], Qo[k], sc[k])
+        say(f"  field {k}: rel L2 {e:.2e}")
+        assert e <= 2e-5, (k, e)
+    assert len(d) == len(dor) == 4
+    top_s, top_d = max(r[1] for r in dor), max(r[2] for r in dor)
+    for r, ro in zip(d, dor):
+        assert r["nonfinite"] == 0
+        assert r["Ek"] == pytest.approx(ro[0], rel=2e-5)
+        assert abs(r["eps_s"] - ro[1]) <= 2e-4 * top_s, (r["step"], r["eps_s"], ro[1])
+        assert abs(r["eps_d"] - ro[2]) <= 2e-3 * top_d, (r["step"], r["eps_d"], ro[2])
 
 
 def test_sod_tube_config():
@@ -277,16 +306,45 @@ def test_errors_and_empty_steps():
 
 
 def test_nonfinite_state_reports_diverged():
+    """A state holding a NaN (restored from a checkpoint: initial fields that are not
+    finite are refused) makes the fused reduction report EDIVERGED."""
     case = inputs.random_smooth(8, 4, 4, seed=1)
-    Q = case.Q0.copy()
-    Q[4, 1, 2, 3] = np.nan
     say("diverged state")
     with binding.Solver(case.params) as s:
-        s.init(Q)
+        s.init(case.Q0)
+        f, st = s.populations()
+        f[30, 1, 2, 3] = np.nan
+        s.set_populations(f, st)
         s.step(3, diag_every=1)
         recs, status = s.diagnostics()
     assert status == binding.LBM_EDIVERGED
     assert recs[0]["nonfinite"] >= 1
+
+
+def test_unphysical_initial_fields_are_refused():
+    """lbm_init_fields refuses (EINVAL) initial fields with a non-finite value, a
+    non-positive density or a non-positive pressure, and leaves the context
+    uninitialised."""
+    case = inputs.random_smooth(8, 4, 4, seed=2)
+    bad = []
+    for what in ("nan", "rho", "p"):
+        Q = case.Q0.copy()
+        if what == "nan":
+            Q[4, 1, 2, 3] = np.nan
+        elif what == "rho":
+            Q[0, 3, 1, 0] = -1e-3
+        else:   # total energy at half the kinetic energy: negative pressure at one cell
+            Q[4, 2, 2, 2] = 0.5 * 0.5 * (Q[1:4, 2, 2, 2] ** 2).sum() / Q[0, 2, 2, 2]
+        bad.append((what, Q))
+    for what, Q in bad:
+        say(f"refused initial fields: {what}")
+        with binding.Solver(case.params) as s:
+            with pytest.raises(binding.LbmError) as e:
+                s.init(Q)
+            assert e.value.status == binding.LBM_EINVAL, what
+            with pytest.raises(binding.LbmError) as e2:
+                s.step(1)
+            assert e2.value.status == binding.LBM_ESTATE
 
 
 def test_full_size_sampled_cells_256():

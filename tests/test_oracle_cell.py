@@ -112,16 +112,17 @@ def moments(f):
 
 # ----------------------------------------------------------------------------
 def test_lattice_and_equilibrium_moments():
-    """P1/P2: the initial equilibrium carries Q in the zeroth moment, the advective
-    flux in the first and c_s^2 Q I in the second."""
-    prm = params(nx=3, ny=2, nz=2)
+    """P1/P2: the equilibrium carries Q in the zeroth moment, the advective flux in
+    the first and c_s^2 Q I in the second (the start of a uniform state is its
+    equilibrium; each cell of a 1x1x1 periodic grid is a uniform state)."""
+    prm = params(nx=1, ny=1, nz=1)
     rng = np.random.default_rng(1)
-    Q = np.stack([state(s) for s in range(12)], axis=1).reshape(5, 2, 2, 3)
+    Q = np.stack([state(s) for s in range(12)], axis=1)
     Q += 1e-3 * rng.standard_normal(Q.shape)
-    f = oracle.init(prm, Q)
     for n in range(12):
-        q = Q.reshape(5, -1)[:, n]
-        m0, m1, m2 = moments(f[:, n])
+        q = Q[:, n]
+        f = oracle.init(prm, q.reshape(5, 1, 1, 1))
+        m0, m1, m2 = moments(f[:, 0])
         np.testing.assert_allclose(m0, q, rtol=1e-14, atol=1e-16)
         np.testing.assert_allclose(m1, flux_adv(q), rtol=1e-13, atol=1e-17)
         for k in range(5):
@@ -173,9 +174,10 @@ def test_exact_gradient_recovery(seed, omega):
 
 
 def test_momentum_block_damps_only_sym_dev():
-    """Sec. 2.4: with rho uniform and u = 0, vorticity and dilatation pass through the
-    momentum block unchanged and the symmetric-deviatoric strain is scaled by
-    1/(1+beta), beta = 2 nu omega / c_s^2 (eq. 6)."""
+    """Sec. 2.4, eq. 6: with rho uniform and u = 0 the momentum block leaves the
+    antisymmetric part (rotation) and the trace (expansion) of the direct gradient as
+    they are and divides its traceless symmetric part by 1 + beta,
+    beta = 2 nu omega / c_s^2."""
     omega = 1.95
     prm = params(mu_law=0, mu_ref=0.04, omega=[omega] * 5)
     Q = np.array([1.0, 0.0, 0.0, 0.0, 0.005 / (GAMMA - 1)])
