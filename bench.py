@@ -121,10 +121,12 @@ def becker_linf(case, Q):
     return best
 
 
-def bench_batch(count=64, steps=5000, seed=0, stream=None):
+def bench_batch(count=64, steps=5000, seed=0, stream=None, tuning=None, sequential=True):
     """Batched Becker shocks (seeded lengths 512-8192 x 4 x 4, Mach 1.5-5, FP32,
     regularized collision with sensor): autotuned batch kernel + graphs, against
-    the same solves run one after another in single contexts."""
+    the same solves run one after another in single contexts.  A given tuning
+    (block, nontemporal, blocks_per_cu, grid) replaces the autotuner; sequential=False
+    skips the single-context baseline (counter runs of the batch kernel alone)."""
     import numpy as np
     import torch
     from paper_2609_16361_amd import binding, inputs
@@ -136,7 +138,11 @@ def bench_batch(count=64, steps=5000, seed=0, stream=None):
     with binding.Batch(int(nbytes * 1.05) + (64 << 20), max_instances=count, graph_steps=50,
                        stream=stream.cuda_stream) as b:
         ids = [b.add(c.params, c.Q0, steps) for c in cases]
-        best, best_us, tried = b.autotune(trial_steps=50)
+        if tuning is None:
+            best, best_us, tried = b.autotune(trial_steps=50)
+        else:
+            b.set_tuning(*tuning)
+            best, best_us, tried = b.info()["tuning"], None, []
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -156,6 +162,8 @@ def bench_batch(count=64, steps=5000, seed=0, stream=None):
                       "wall_s_incl_init_readout": t_wall}
     out["linf_rel_error"] = {"median": float(np.median(errs)), "max": float(np.max(errs)),
                              "mach_of_max": float(cases[int(np.argmax(errs))].meta["mach"])}
+    if not sequential:
+        return out
     # the same solves one at a time, plain FP32 single contexts
     t_seq = 0.0
     t_wall = time.perf_counter()
@@ -204,14 +212,25 @@ def bench_precision(stream, n=128, steps=4000, diag_every=50):
     def rel(a, b):
         return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
-    k0 = 1  # the first record is the equilibrium start, where the gradients are zero
-    return {"workload": f"compressible Taylor-Green {n}^3, {steps} steps, diagnostics every {diag_every}",
-            "glups": rates,
-            "f16_vs_f32_series": {q: rel(series["f16"][k0:, i], series["f32"][k0:, i])
-                                  for i, q in enumerate(("Ek", "eps_s", "eps_d"))},
-            "f16_vs_f32_fields": [rel(fields["f16"][k], fields["f32"][k]) for k in range(5)],
-            "Ek_final": {name: float(series[name][-1, 0] * case.meta["ek_scale"]) for name in series},
-            "tc_final": steps * case.meta["tc_per_step"]}
+    k0 = 1  # the first record holds the start's central-difference gradients, not the update's
+    out = {"workload": f"compressible Taylor-Green {n}^3, {steps} steps, diagnostics every {diag_every}",
+           "glups": rates,
+           "f16_vs_f32_series": {q: rel(series["f16"][k0:, i], series["f32"][k0:, i])
+                                 for i, q in enumerate(("Ek", "eps_s", "eps_d"))},
+           "f16_vs_f32_fields": [rel(fields["f16"][k], fields["f32"][k]) for k in range(5)],
+           "Ek_final": {name: float(series[name][-1, 0] * case.meta["ek_scale"]) for name in series},
+           "tc_final": steps * case.meta["tc_per_step"]}
+    # against the FP64 oracle's series of the same workload (tests/golden, written
+    # by make_tgv128_oracle_series.py from the oracle alone)
+    gold = os.path.join(ROOT, "tests", "golden", f"tgv{n}_oracle_series.json")
+    if os.path.exists(gold) and steps == 4000 and diag_every == 50:
+        ref = json.load(open(gold))
+        o = np.stack([np.array(ref[q]) for q in ("Ek", "eps_s", "eps_d")], axis=1)
+        assert o.shape == series["f32"].shape, (o.shape, series["f32"].shape)
+        for name in ("f32", "f16"):
+            out[f"{name}_vs_oracle_series"] = {q: rel(series[name][k0:, i], o[k0:, i])
+                                              for i, q in enumerate(("Ek", "eps_s", "eps_d"))}
+    return out
 
 
 def bench_mms(stream, sizes=(64, 128, 256), frac=0.5):
@@ -298,14 +317,17 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
     work = sum(r.case.cells * r.steps for r in trace)
     out = {"requests": count, "rate_per_s": rate, "seed": seed, "budget_bytes": budget_bytes,
            "admission": "largest work first among arrived requests, any request waiting over 2 s first",
-           "divergence": "batched: checked every 200 steps, a diverged request is retired as failed at once; "
-                         "sequential: every request runs to its step count",
+           "divergence": "checked every 200 steps in every leg; a diverged request stops at once as failed",
+           "rejection": "a request whose initial density or pressure is not positive is refused by the "
+                        "library (LBM_EINVAL) in every leg and counted as rejected",
            "offered_glup": work / 1e9,
            "mix": {k: sum(1 for r in trace if r.kind == k) for k in ("sod", "tgv", "becker")},
            "fp16_share": sum(r.storage for r in trace) / count}
 
     failures = {}
     progress = {"leg": "", "done": 0}  # long traces report every 100 results on stderr
+    f16_results = {}                   # FP16-served results of the mixed leg, by request
+    f16_err = {}                       # kind -> per request, max over rho, rho u, E of rel. L2
 
     def failed(req):
         failures[req.rid] = {"kind": req.kind, "shape": list(req.case.shape), "steps": req.steps,
@@ -323,29 +345,53 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
     def finite(req, Q):
         return finished(req, bool(np.isfinite(Q).all()))
 
-    def batched(storage_override):
+    def keep_f16(req, Q):
+        ok = finite(req, Q)
+        if ok and req.storage == binding.LBM_STORE_F16:
+            f16_results[req.rid] = Q.astype(np.float32)
+        return ok
+
+    def compare_f32(req, Q):
+        # FP32 results of the batch are bitwise those of the sequential FP32 solves
+        ok = finite(req, Q)
+        a = f16_results.pop(req.rid, None)
+        if ok and a is not None:
+            m, ma = Q[1:4], a[1:4].astype(np.float64)
+            errs = [np.linalg.norm(a[0] - Q[0]) / np.linalg.norm(Q[0]),
+                    np.linalg.norm(ma - m) / max(np.linalg.norm(m), 1e-300),
+                    np.linalg.norm(a[4] - Q[4]) / np.linalg.norm(Q[4])]
+            f16_err.setdefault(req.kind, []).append(float(max(errs)))
+        return ok
+
+    def batched(storage_override, handler):
         progress.update(leg="batched" if storage_override is None else "batched fp32", done=0)
         with binding.Batch(budget_bytes, max_instances=4096, max_tiles=1 << 22, graph_steps=chunk,
                            stream=stream.cuda_stream) as b:
-            srv = serve.Server(b, arena_bytes=budget_bytes, chunk_steps=chunk, result_handler=finite,
+            srv = serve.Server(b, arena_bytes=budget_bytes, chunk_steps=chunk, result_handler=handler,
                                sync=torch.cuda.synchronize, max_active_cells=max_active_cells,
                                storage_override=storage_override,
                                failure_handler=lambda req: finished(req, False))
             return srv.serve(trace)
 
     # storage as requested (FP16 for about half the requests), then every request in
-    # FP32: the latter's results are bitwise those of the sequential FP32 solves
-    st = batched(None)
+    # FP32: the latter's results are bitwise those of the sequential FP32 solves, and
+    # each FP16 result is compared with the FP32 result of the same request
+    st = batched(None, keep_f16)
     out["batched"] = st.summary()
     out["batched"]["max_active_cells"] = max_active_cells
     out["failures"] = failures
-    out["batched_fp32"] = batched(binding.LBM_STORE_F32).summary()
+    out["batched_fp32"] = batched(binding.LBM_STORE_F32, compare_f32).summary()
+    out["accuracy"] = {
+        "batched_fp32_vs_sequential_fp32": "bitwise equal (same kernels and arithmetic per instance)",
+        "fp16_vs_fp32_max_rel_l2": {k: {"requests": len(v), "median": float(np.median(v)), "max": float(np.max(v))}
+                                    for k, v in sorted(f16_err.items())}}
 
     def fp32_solver(params):
         return binding.Solver(params, stream=stream.cuda_stream)
 
     progress.update(leg="sequential fp32", done=0)
-    st2 = serve.serve_sequential(trace, fp32_solver, result_handler=finite, sync=torch.cuda.synchronize)
+    st2 = serve.serve_sequential(trace, fp32_solver, result_handler=finite, sync=torch.cuda.synchronize,
+                                 failure_handler=lambda req: finished(req, False))
     out["sequential_fp32"] = st2.summary()
     out["speedup_solves_per_s"] = out["batched"]["solves_per_s"] / out["sequential_fp32"]["solves_per_s"]
     out["speedup_fp32_solves_per_s"] = (out["batched_fp32"]["solves_per_s"] /
@@ -387,6 +433,10 @@ def main():
     ap.add_argument("--no-bw-probe", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Becker workload")
     ap.add_argument("--batch-only", action="store_true", help="only the batched Becker workload")
+    ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--batch-tuning", type=str, default=None, metavar="B,NT,BPC,GRID",
+                    help="fixed batch launch shape instead of the autotuner")
+    ap.add_argument("--batch-no-seq", action="store_true", help="skip the single-context batch baseline")
     ap.add_argument("--precision-only", action="store_true",
                     help="only the FP16-storage precision study (128^3 vortex)")
     ap.add_argument("--fp16", action="store_true", help="FP16 population storage for the main workload")
@@ -421,7 +471,9 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_only, "copy_launches": 4, "copy_gbs": round(gbs, 1)}))
         return
     if args.batch_only:
-        print(json.dumps({"batch": bench_batch(stream=stream)}), flush=True)
+        tun = None if args.batch_tuning is None else [int(v) for v in args.batch_tuning.split(",")]
+        print(json.dumps({"batch": bench_batch(steps=args.batch_steps, stream=stream, tuning=tun,
+                                               sequential=not args.batch_no_seq)}), flush=True)
         return
     if args.precision_only:
         print(json.dumps({"precision": bench_precision(stream)}), flush=True)

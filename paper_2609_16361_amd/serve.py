@@ -17,7 +17,11 @@ ones.  order="fifo" admits strictly in arrival order.
 
 A request whose state stops being finite (the scheme has diverged) is retired as
 failed at the next divergence check (every 200 steps by default), rather than
-occupying the device until its step count.
+occupying the device until its step count.  A request the library refuses at
+admission (an initial state with non-positive density or pressure, or one larger
+than the whole budget) is rejected: it never runs and is counted apart from the
+failures.  The sequential baseline applies the same divergence check and the
+same rejection.
 
 The loop runs on the wall clock (arrival times are seconds after start); latency
 is completion minus arrival.  A stand-in backend with the same methods as
@@ -31,7 +35,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-ENOMEM = -2  # lbm_status LBM_ENOMEM
+EINVAL, ENOMEM = -1, -2  # lbm_status LBM_EINVAL, LBM_ENOMEM
 
 
 @dataclass
@@ -46,6 +50,7 @@ class Outcome:
     completed: float = math.nan
     ok: bool = False
     result: object = None       # whatever the result handler returned
+    rejected: str = ""          # why admission refused it ("" = admitted)
 
     @property
     def latency(self) -> float:
@@ -66,13 +71,17 @@ class ServeStats:
 
     def summary(self) -> dict:
         done = [o for o in self.outcomes if o.ok]
+        rejected = [o for o in self.outcomes if o.rejected]
         lat = np.array([o.latency for o in done]) if done else np.array([math.nan])
         first = min(o.arrival for o in self.outcomes) if self.outcomes else 0.0
         last = max((o.completed for o in done), default=first)
         span = max(last - first, 1e-9)
         lups = sum(o.cells * o.steps for o in done)
         return {"requests": len(self.outcomes), "completed": len(done),
-                "failed": len(self.outcomes) - len(done),
+                "failed": len(self.outcomes) - len(done) - len(rejected),
+                "rejected": len(rejected),
+                "rejected_by_kind": {k: sum(1 for o in rejected if o.kind == k)
+                                     for k in sorted({o.kind for o in rejected})},
                 "solves_per_s": len(done) / span, "span_s": span,
                 "glups": lups / span / 1e9,
                 "latency_p50_s": float(np.percentile(lat, 50)),
@@ -125,8 +134,9 @@ class Server:
         # "fifo": admit arrived requests in arrival order, the first that does not
         # fit blocks the rest; "largest": among the arrived requests, largest work
         # (cells x steps) first, skipping those that do not fit yet, except that
-        # requests waiting longer than max_wait_s go first in arrival order (so a
-        # stream of large requests cannot hold a small one back without bound)
+        # requests waiting longer than max_wait_s go first in arrival order and keep
+        # their place while they do not fit (so neither a stream of large requests
+        # nor one of small ones can hold a request back without bound)
         if order not in ("fifo", "largest"):
             raise ValueError(f"order must be 'fifo' or 'largest', not {order!r}")
         self.order = order
@@ -136,6 +146,12 @@ class Server:
         # 64-request serving mix): once per chunk cost 1-2% of its throughput
         self.check_chunks = max(1, -(-int(check_steps) // self.chunk))
         self.on_failure = failure_handler
+
+    @staticmethod
+    def _reject(o: Outcome, now: float, why: str) -> None:
+        o.ok = False
+        o.completed = now
+        o.rejected = why or "rejected"
 
     def serve(self, requests) -> ServeStats:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -151,6 +167,7 @@ class Server:
             now = self.clock() - t0
             # admission: arrived requests while memory and the cell cap allow
             arrived = [r for r in pending if r.arrival <= now]
+            overdue = []
             if self.order == "largest":
                 overdue = [r for r in arrived if self.max_wait is not None and now - r.arrival > self.max_wait]
                 rest = sorted((r for r in arrived if r not in overdue), key=lambda r: -r.case.cells * r.steps)
@@ -158,8 +175,7 @@ class Server:
             for r in arrived:
                 nb = state_bytes(r.case.params, stg[r.rid])
                 if nb > self.arena_bytes:
-                    out[r.rid].ok = False        # can never fit: rejected
-                    out[r.rid].completed = now
+                    self._reject(out[r.rid], now, "larger than the HBM budget")
                     pending.remove(r)
                     continue
                 fits = used_bytes + nb <= self.arena_bytes and len(active) < self.max_instances and not (
@@ -168,12 +184,22 @@ class Server:
                     try:
                         iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=stg[r.rid])
                     except RuntimeError as e:
+                        status = getattr(e, "status", None)
+                        if status == EINVAL:
+                            # the library refuses the request itself (e.g. an initial
+                            # state with non-positive density or pressure)
+                            self._reject(out[r.rid], self.clock() - t0, str(e))
+                            pending.remove(r)
+                            continue
                         # no free run of that size yet (fragmentation): wait for retirements
-                        if getattr(e, "status", None) != ENOMEM or not active:
+                        if status != ENOMEM or not active:
                             raise
                         fits = False
                 if not fits:
-                    if self.order == "fifo":
+                    if self.order == "fifo" or r in overdue:
+                        # an overdue request keeps its place: nothing behind it is
+                        # admitted until it fits, so later arrivals cannot take the
+                        # memory it waits for
                         break
                     continue
                 pending.remove(r)
@@ -228,9 +254,15 @@ class Server:
 
 
 def serve_sequential(requests, solver_factory, result_handler=None, clock=time.perf_counter,
-                     sync=None) -> ServeStats:
+                     sync=None, stop_diverged: bool = True, check_steps: int = 200,
+                     failure_handler=None) -> ServeStats:
     """Baseline: the same requests one at a time in arrival order, each in its own
-    single context made by solver_factory(params) (plain FP32)."""
+    single context made by solver_factory(params) (plain FP32).  With stop_diverged
+    a request steps in pieces of check_steps, each carrying the fused diagnostic
+    reduction on its first step, and one whose non-finite count is positive stops
+    there as failed (the batched server's check, at the same interval).  A request
+    the library refuses at initialisation (LBM_EINVAL) is rejected, as in the
+    server."""
     handle = result_handler or (lambda req, Q: bool(np.isfinite(Q).all()))
     sync = sync or (lambda: None)
     reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -241,17 +273,38 @@ def serve_sequential(requests, solver_factory, result_handler=None, clock=time.p
         if r.arrival > now:
             time.sleep(r.arrival - now)
         o = Outcome(r.rid, r.kind, 0, r.case.cells, r.steps, r.arrival)
+        st.outcomes.append(o)
+        st.max_active = 1
         o.admitted = clock() - t0
         with solver_factory(r.case.params) as s:
-            s.init(r.case.Q0)
-            s.step(r.steps)
+            try:
+                s.init(r.case.Q0)
+            except RuntimeError as e:
+                if getattr(e, "status", None) != EINVAL:
+                    raise
+                Server._reject(o, clock() - t0, str(e))
+                continue
+            diverged = False
+            if stop_diverged:
+                done = 0
+                while done < r.steps and not diverged:
+                    k = min(int(check_steps), r.steps - done)
+                    s.step(k, int(check_steps))
+                    done += k
+                    recs, _ = s.diagnostics()
+                    diverged = any(rec["nonfinite"] > 0 for rec in recs)
+            else:
+                s.step(r.steps)
             sync()
-            Q = s.moments()
+            Q = None if diverged else s.moments()
         o.completed = clock() - t0
+        if diverged:
+            st.stopped += 1
+            if failure_handler is not None:
+                failure_handler(r)
+            continue
         res = handle(r, Q)
         o.ok = bool(res) if isinstance(res, (bool, np.bool_)) else True
         o.result = res
-        st.outcomes.append(o)
-        st.max_active = 1
     st.wall_s = clock() - t0
     return st

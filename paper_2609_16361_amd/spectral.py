@@ -1,8 +1,8 @@
 """Spectral dissipation channels of a periodic state (post-processing, Sec. 3.3).
 
-The paper evaluates the solenoidal and dilatational dissipation spectrally, as the
-reference solvers do, because a finite-difference dilatation under-reads the
-shocklets.  The step kernels report the same channels from the gradients they
+Sec. 3.3 evaluates the solenoidal and dilatational dissipation with Fourier
+derivatives, like the solvers it compares with; a difference stencil would smear
+the weak embedded shocks and bias the dilatational channel low.  The step kernels report the same channels from the gradients they
 reconstruct in the collision; this module recomputes them from the conserved
 fields alone (the output of lbm_moments), with exact Fourier derivatives on the
 periodic lattice:

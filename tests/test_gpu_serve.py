@@ -14,14 +14,17 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("stop_diverged", [True, False])
 def test_results_alone_equal_in_mix(stop_diverged):
     """Each result in the mix is bitwise the request's result alone.  The mix holds
-    Mach 1.5 vortices whose isothermal initial pressure is negative; one on 16^3 of
-    200 steps stops being finite early (at step 12 in the FP64 oracle).  With the
-    divergence check a diverged request is retired early as failed (no result);
-    without it, it runs to its step count and its non-finite state is bitwise the
-    one alone."""
+    a Mach 1.5 vortex whose isothermal initial pressure is negative: the library
+    refuses it (LBM_EINVAL), in the mix and alone, and the server counts it as
+    rejected.  It also holds a 16^3 vortex of 200 steps run at 0.3 cells per step,
+    which stops being finite early (by step 60 in the FP64 oracle).  With the
+    divergence check that request is retired early as failed (no result); without
+    it, it runs to its step count and its non-finite state is bitwise the one
+    alone."""
     trace = inputs.serving_trace(count=12, rate=400.0, seed=5, steps_range=(40, 400),
                                  tgv_n=(12, 20), sod_n=(64, 300), becker_L=(64, 200))
-    early = inputs.Request(100, 0.0, "tgv", inputs.tgv(n=16, mach=1.5, steps=200, diag_every=0), 200, 0)
+    early = inputs.Request(100, 0.0, "tgv", inputs.tgv(n=16, mach=1.25, cfl=0.3, steps=200, diag_every=0),
+                           200, 0)
     trace.append(early)
     results, stopped = {}, []
 
@@ -37,10 +40,17 @@ def test_results_alone_equal_in_mix(stop_diverged):
     s = st.summary()
     print(s, flush=True)
     assert st.max_active >= 3    # requests overlapped
-    finite_alone = 0
+    outcome = {o.rid: o for o in st.outcomes}
+    finite_alone = rejected_alone = 0
     for r in trace:
         with binding.Solver(r.case.params, storage=r.storage) as one:
-            one.init(r.case.Q0)
+            try:
+                one.init(r.case.Q0)
+            except binding.LbmError as e:
+                assert e.status == binding.LBM_EINVAL
+                rejected_alone += 1
+                assert outcome[r.rid].rejected and r.rid not in results, r.rid
+                continue
             one.step(r.steps)
             Q = one.moments()
         finite = bool(np.isfinite(Q).all())
@@ -50,6 +60,7 @@ def test_results_alone_equal_in_mix(stop_diverged):
         else:
             # retired early: it diverged alone as well
             assert stop_diverged and not finite and r.rid in {x.rid for x in stopped}, (r.rid, r.kind)
+    assert rejected_alone >= 1 and s["rejected"] == rejected_alone
     assert s["completed"] == finite_alone and s["completed"] >= len(trace) - 3
     assert s["stopped_diverged"] == len(stopped)
     assert (early.rid in {x.rid for x in stopped}) == stop_diverged

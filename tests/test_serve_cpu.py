@@ -100,6 +100,34 @@ def test_cell_cap_and_rejection():
     st = srv.serve(reqs)
     assert st.max_active == 1                     # the cell cap admits one at a time
     assert [o.ok for o in st.outcomes] == [True, True, False]   # the big one never fits
+    assert st.outcomes[2].rejected and st.summary()["rejected"] == 1 and st.summary()["failed"] == 0
+
+
+class Refused(RuntimeError):
+    status = -1   # LBM_EINVAL
+
+
+class FakeRefusingBatch(FakeBatch):
+    """Refuses (LBM_EINVAL) requests whose steps are in `refuse`."""
+
+    def __init__(self, clock, refuse):
+        super().__init__(clock)
+        self.refuse = refuse
+
+    def add(self, params, Q, steps, storage=0):
+        if steps in self.refuse:
+            raise Refused("initial pressure not positive")
+        return super().add(params, Q, steps, storage)
+
+
+def test_refused_request_is_rejected_not_failed():
+    clk = FakeClock()
+    fb = FakeRefusingBatch(clk, refuse={30})
+    reqs = [make_req(0, 0.0, 320, 20), make_req(1, 0.0, 320, 30), make_req(2, 0.0, 320, 40)]
+    st = serve.Server(fb, arena_bytes=1 << 30, chunk_steps=10, clock=clk, order="fifo").serve(reqs)
+    s = st.summary()
+    assert s["completed"] == 2 and s["rejected"] == 1 and s["failed"] == 0
+    assert "pressure" in st.outcomes[1].rejected and fb.added_steps == [20, 40]
 
 
 def test_largest_work_first_skips_what_does_not_fit():
@@ -130,6 +158,27 @@ def test_largest_work_first_with_a_wait_bound():
     assert order_of(0.05) == [200, 5, 150]     # both overdue: arrival order
 
 
+def test_overdue_request_keeps_its_place():
+    """A large request that is overdue and does not fit blocks admission behind it,
+    so a stream of small requests arriving later cannot take the memory it waits
+    for: it starts as soon as the running work leaves room."""
+    def run(max_wait):
+        clk = FakeClock()
+        fb = FakeBatch(clk)
+        small = [make_req(i, 0.002 * i, 320, 30) for i in range(40)]          # arrive through 0.08 s
+        big = make_req(99, 0.001, 3200, 20)
+        one_small = serve.state_bytes(small[0].case.params, 0)
+        budget = serve.state_bytes(big.case.params, 0) + one_small
+        st = serve.Server(fb, arena_bytes=budget - 1, chunk_steps=10, clock=clk, order="largest",
+                          max_wait_s=max_wait).serve(small + [big])
+        return {o.rid: o for o in st.outcomes}
+    waited = run(0.01)[99]
+    # its wait is bounded by max_wait plus the 30 ms the small solves already running need
+    assert waited.ok and waited.admitted - waited.arrival <= 0.01 + 0.03 + 0.01
+    starved = run(None)[99]
+    assert starved.admitted > 0.08 > waited.admitted     # without the bound it waits for every small one
+
+
 def test_unknown_order_rejected():
     with pytest.raises(ValueError):
         serve.Server(FakeBatch(FakeClock()), arena_bytes=1, order="random")
@@ -151,9 +200,12 @@ def test_sequential_baseline_fifo():
         def init(self, Q):
             self.Q = Q
 
-        def step(self, n):
+        def step(self, n, diag_every=0):
             self.n += n
             clk.t += n * 1e-3
+
+        def diagnostics(self):
+            return [], 0
 
         def moments(self):
             return self.Q + self.n
@@ -163,6 +215,55 @@ def test_sequential_baseline_fifo():
     lat = [o.latency for o in st.outcomes]
     assert lat == sorted(lat)                      # FIFO: later requests wait longer
     assert st.summary()["completed"] == 4
+
+
+def test_sequential_baseline_stops_diverged_and_rejects():
+    """The baseline checks divergence at the server's interval (a fused diagnostic
+    reduction on the first step of every check_steps piece) and rejects a request
+    the library refuses at initialisation."""
+    clk = FakeClock()
+
+    class Solver:
+        def __init__(self, params):
+            self.n, self.recs, self.bad_from = 0, [], params.get("bad_from")
+            self.refuse = params.get("refuse", False)
+
+        def __enter__(self):
+            return self
+
+        def __exit__(self, *a):
+            pass
+
+        def init(self, Q):
+            if self.refuse:
+                raise Refused("initial density not positive")
+
+        def step(self, n, diag_every=0):
+            for t in range(self.n, self.n + n):
+                if diag_every and t % diag_every == 0:
+                    self.recs.append({"step": t, "nonfinite": int(self.bad_from is not None and t >= self.bad_from)})
+            self.n += n
+            clk.t += n * 1e-3
+
+        def diagnostics(self):
+            r, self.recs = self.recs, []
+            return r, 0
+
+        def moments(self):
+            return np.zeros((5, 4, 4, 20)) + self.n
+
+    reqs = [make_req(0, 0.0, 320, 1000), make_req(1, 0.0, 320, 500), make_req(2, 0.0, 320, 100)]
+    reqs[0].case.params["bad_from"] = 250          # diverges after 250 steps
+    reqs[1].case.params["refuse"] = True
+    failed = []
+    st = serve.serve_sequential(reqs, Solver, clock=clk, check_steps=200, failure_handler=failed.append)
+    o0, o1, o2 = st.outcomes
+    assert not o0.ok and not o0.rejected and o0.completed == pytest.approx(0.6)   # stopped at step 600
+    assert o1.rejected and not o1.ok
+    assert o2.ok
+    s = st.summary()
+    assert (s["completed"], s["failed"], s["rejected"], s["stopped_diverged"]) == (1, 1, 1, 1)
+    assert [r.rid for r in failed] == [0]
 
 
 def test_serving_trace_mix():
