@@ -47,16 +47,16 @@ lbm_status validate(const lbm_params* p) {
     if (p->bc[a] == LBM_BC_ZERO_GRADIENT && dims[a] < 2)
       return fail(LBM_EINVAL, "zero-gradient axis %d needs >= 2 cells (got %d)", a, dims[a]);
   }
-  // the step kernels index cells in 32 bits, and a tile's end (its first cell plus
-  // up to 1024) must stay representable: grids up to 2^31 - 2^16 cells (1290^3)
-  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-  if (N > (int64_t)INT32_MAX - 65535)
-    return fail(LBM_EINVAL, "grid of %lld cells exceeds the 32-bit cell index range", (long long)N);
-
   if (p->collision != LBM_COLL_RLB_SENSOR && p->collision != LBM_COLL_BGK)
     return fail(LBM_EINVAL, "collision = %d is not an lbm_collision", p->collision);
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F16)
     return fail(LBM_EINVAL, "storage = %d is not an lbm_storage", p->storage);
+  // the step kernels index array elements in 32 bits, and a tile's end (its first
+  // element plus up to 1024) must stay representable: grids whose padded rows span
+  // up to 2^31 - 2^16 elements (about 1290^3)
+  const int64_t NE = row_pitch(p) * p->ny * p->nz;
+  if (NE > (int64_t)INT32_MAX - 65535)
+    return fail(LBM_EINVAL, "grid of %lld elements exceeds the 32-bit index range", (long long)NE);
   if (p->mu_law != LBM_MU_CONSTANT && p->mu_law != LBM_MU_SUTHERLAND)
     return fail(LBM_EINVAL, "mu_law = %d is not an lbm_mu_law", p->mu_law);
   if (p->layout_pad < 0) return fail(LBM_EINVAL, "layout_pad must be >= 0");
@@ -99,8 +99,20 @@ lbm_status check_fields(const lbm_params* p, const double* Q) {
   return LBM_OK;
 }
 
+int64_t row_pitch(const lbm_params* p) {
+  // rows padded to whole 128-byte lines when the padding is at most an eighth of
+  // the row (a grid of one row has no +-y or +-z neighbours to align) ...
+  const int64_t nx = p->nx;
+  if ((int64_t)p->ny * p->nz == 1) return nx;
+  const int64_t line = p->storage == LBM_STORE_F16 ? 64 : 32;
+  const int64_t px = (nx + line - 1) / line * line;
+  // ... and never where the padding alone would leave the 32-bit index range
+  if (8 * (px - nx) > nx || px * p->ny * p->nz > (int64_t)INT32_MAX - 65535) return nx;
+  return px;
+}
+
 int64_t slot_stride(const lbm_params* p) {
-  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  const int64_t N = row_pitch(p) * p->ny * p->nz;
   const int64_t el = p->storage == LBM_STORE_F16 ? 2 : 4;
   const int64_t align = 256 / el;  // arrays start on 256-byte boundaries
   const int64_t s = N + p->layout_pad;
@@ -213,6 +225,8 @@ Grid make_grid(const lbm_params* p) {
   g.zg_y = p->bc[1] == LBM_BC_ZERO_GRADIENT;
   g.zg_z = p->bc[2] == LBM_BC_ZERO_GRADIENT;
   g.S = slot_stride(p);
+  g.px = (int32_t)row_pitch(p);
+  g.pad_ = 0;
   return g;
 }
 

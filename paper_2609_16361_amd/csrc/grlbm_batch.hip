@@ -34,14 +34,14 @@ struct BatchInst {
   int64_t off;      // element offset of the instance's slot 0 in the arena
   int64_t t_start;  // clock value at which the instance was at its step 0
   int64_t t_end;    // clock value at which it has completed all its steps
-  double inv_nx;    // 1/nx and 1/ny for the cell-index decomposition
+  double inv_px;    // 1/px and 1/ny for the element-index decomposition
   double inv_ny;
-  int32_t cells;    // nx * ny * nz
+  int32_t cells;    // px * ny * nz: the elements the instance's rows span
   int32_t pad_;
 };
 
-// A tile is `blockDim.x` consecutive cell indices of one instance (it may span
-// several x-rows), so short rows leave no lane idle.
+// A tile is `blockDim.x` consecutive element indices of one instance (it may span
+// several x-rows; lanes on a row's padding have no cell).
 struct BatchTile {
   int32_t inst;
   int32_t tile;  // tile index within the instance: cells [tile * blockDim.x, ...)
@@ -77,12 +77,13 @@ __global__ void __launch_bounds__(1024) k_batch_step(T* __restrict__ arena, cons
     if (t < ts || t >= I->t_end) continue;  // the same for the whole block
     const int n0 = bt.tile * (int)blockDim.x;
     const int n = n0 + (int)threadIdx.x;
-    const bool act = n < I->cells;
+    bool act = n < I->cells;
     const Grid g = I->g;
     int x = 0, y = 0, z = 0;
     if (act) {
-      const int row = div_exact(n, g.nx, I->inv_nx, x);
+      const int row = div_exact(n, g.px, I->inv_px, x);
       z = div_exact(row, g.ny, I->inv_ny, y);
+      act = x < g.nx;  // the row's padding holds no cell
     }
     const Coll c = I->c;
     T* F = arena + I->off;
@@ -116,6 +117,7 @@ struct CheckItem {
   int32_t c0, c1;
   int32_t f16;
   int32_t flag;
+  int32_t nx, px;  // row length and pitch: elements with (e mod px) >= nx are padding
 };
 constexpr int32_t kCheckRun = 16384;   // cells per item
 constexpr int32_t kCheckBlocks = 16;   // blocks per item (256 lanes, 4 cells each)
@@ -134,6 +136,7 @@ __global__ void __launch_bounds__(256) k_batch_nonfinite(const char* __restrict_
   bool bad = false;
   for (int32_t c = it.c0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); c < it.c1;
        c += (int32_t)(gridDim.x * blockDim.x)) {
+    if (c % it.px >= it.nx) continue;
 #pragma unroll
     for (int k = 0; k < kFields; ++k) {
       const int64_t e = it.off + (int64_t)(7 * k) * it.S + c;
@@ -199,7 +202,7 @@ struct lbm_batch {
 namespace {
 
 int64_t inst_tiles(const lbm_params* p, int block) {
-  const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+  const int64_t n = grlbm::row_pitch(p) * p->ny * p->nz;
   return (n + block - 1) / block;
 }
 
@@ -512,8 +515,8 @@ lbm_status lbm_batch_add(lbm_batch* b, const lbm_params* p, const double* Q, int
   h.d.t_start = b->clock;
   h.d.t_end = b->clock + steps;
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-  h.d.cells = (int32_t)N;
-  h.d.inv_nx = 1.0 / p->nx;
+  h.d.cells = (int32_t)grlbm::row_cells(h.d.g);
+  h.d.inv_px = 1.0 / h.d.g.px;
   h.d.inv_ny = 1.0 / p->ny;
   double* dq = nullptr;
   if (hipMalloc((void**)&dq, sizeof(double) * 5 * (size_t)N) != hipSuccess) {
@@ -613,7 +616,7 @@ lbm_status lbm_batch_nonfinite(lbm_batch* b, int32_t* ids, int32_t max, int32_t*
     const int32_t f16 = h.p.storage == LBM_STORE_F16 ? 1 : 0;
     for (int32_t c0 = 0; c0 < h.d.cells; c0 += grlbm::kCheckRun)
       items.push_back({h.d.off, h.d.g.S, c0, c0 + std::min(grlbm::kCheckRun, h.d.cells - c0), f16,
-                       (int32_t)which.size()});
+                       (int32_t)which.size(), h.d.g.nx, h.d.g.px});
     which.push_back(id);
   }
   const int32_t n = (int32_t)which.size();  // at most max_inst flags

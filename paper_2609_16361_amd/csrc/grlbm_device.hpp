@@ -5,7 +5,11 @@
 // Layout.  Populations are 35 arrays ("slots"), slot s = 7 k + i for field k
 // (rho, rho u_x, rho u_y, rho u_z, E) and D3Q7 direction i (0, +x, -x, +y, -y, +z,
 // -z); array s starts at element s * S, and cell (x, y, z) sits at element
-// x + nx (y + ny z) of every array.  Each stored value is g = f - w_i Q_ref,k.
+// x + px (y + ny z) of every array, where the row pitch px >= nx pads each x-row to
+// a whole number of 128-byte lines when that costs at most an eighth of the row
+// (so the +-y and +-z neighbours of an aligned run of cells are aligned runs too);
+// elements x in [nx, px) are padding that no update reads or writes.  Each stored
+// value is g = f - w_i Q_ref,k.
 //
 // AA pattern (one buffer, updated in place).  At even parity slot i of cell x holds
 // f_i(x).  An even step reads the cell's own slots and writes f*_i to its own slot
@@ -52,7 +56,12 @@ struct Grid {
   int32_t nx, ny, nz;
   int32_t zg_x, zg_y, zg_z;  // zero-gradient flags per axis
   int64_t S;                 // elements between consecutive slot arrays
+  int32_t px;                // row pitch: elements between consecutive x-rows (>= nx)
+  int32_t pad_;
 };
+
+// Elements of one slot array that the grid's rows span (padding included).
+__host__ __device__ __forceinline__ int64_t row_cells(const Grid& g) { return (int64_t)g.px * g.ny * g.nz; }
 
 // Per-lane neighbourhood: the cell index and, for each of the six moving
 // directions, where an odd step reads f_i (slot and cell) and whether the lane sits
@@ -65,12 +74,12 @@ struct Nbr {
 
 __device__ __forceinline__ Nbr make_nbr(const Grid& g, int x, int y, int z) {
   Nbr b;
-  const int32_t plane = g.nx * g.ny;
-  b.n = x + g.nx * (y + g.ny * z);
+  const int32_t plane = g.px * g.ny;
+  b.n = x + g.px * (y + g.ny * z);
   b.xm = (x == 0) ? b.n + (g.nx - 1) : b.n - 1;
   b.xp = (x == g.nx - 1) ? b.n - (g.nx - 1) : b.n + 1;
-  b.ym = (y == 0) ? b.n + g.nx * (g.ny - 1) : b.n - g.nx;
-  b.yp = (y == g.ny - 1) ? b.n - g.nx * (g.ny - 1) : b.n + g.nx;
+  b.ym = (y == 0) ? b.n + g.px * (g.ny - 1) : b.n - g.px;
+  b.yp = (y == g.ny - 1) ? b.n - g.px * (g.ny - 1) : b.n + g.px;
   b.zm = (z == 0) ? b.n + plane * (g.nz - 1) : b.n - plane;
   b.zp = (z == g.nz - 1) ? b.n - plane * (g.nz - 1) : b.n + plane;
   b.lo_x = g.zg_x && x == 0;
@@ -378,9 +387,11 @@ __device__ __forceinline__ void collide(float g[kPop], const Coll& c, CellDiag* 
 // ---------------------------------------------------------------- source term
 // The source S of eq. 1 projected onto the lattice weights and added to the
 // post-collision populations (the collision of Algorithm 1): f*_ki += w_i S_k.  src holds
-// the step's source per cell, src[5][N] with N the cell count, lattice units.
-__device__ __forceinline__ void add_source(float f[kPop], const float* __restrict__ src, int64_t N,
-                                           int64_t n) {
+// the step's source per cell, src[5][nz][ny][nx] (no row padding), lattice units.
+__device__ __forceinline__ void add_source(float f[kPop], const float* __restrict__ src, const Grid& g, int x,
+                                           int y, int z) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t n = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
 #pragma unroll
   for (int k = 0; k < kFields; ++k) {
     const float s = src[k * N + n];
@@ -424,7 +435,7 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
     for (int k = 0; k < 5; ++k) vals[3 + k] = d.dq[k];
     vals[8] = d.nonfinite;
   }
-  if constexpr (SRC) add_source(f, src, (int64_t)g.nx * g.ny * g.nz, b.n);
+  if constexpr (SRC) add_source(f, src, g, x, y, z);
   // store half of AA; FP16 dither keys of the destination cells
   const bool f16 = sizeof(T) == 2;
   const uint32_t hn = f16 ? cell_key(b.n, skey) : 0u;
@@ -480,7 +491,8 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
 // cell n, high half cell n + 1), and a wave moves 256 bytes per array instead of
 // 128.  The two cells are collided one after the other with the same call and
 // rounded with the same per-cell dither as st_pop, so the stored bits are those
-// of cell_update<false, COLL, _Float16, ...>.  Both cells must exist.
+// of cell_update<false, COLL, _Float16, ...>.  Both cells must be cells of the grid
+// (with nx even a pair never reaches into the row padding).
 template <bool NT>
 __device__ __forceinline__ uint32_t ld_pair(const _Float16* p) {
   const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
@@ -530,8 +542,8 @@ __device__ __forceinline__ void pair_update_even(_Float16* __restrict__ F, const
     const int cell = n + h;
     bool lo_x = false, hi_x = false, lo_y = false, hi_y = false, lo_z = false, hi_z = false;
     if constexpr (ZG) {
-      const int row = cell / g.nx;
-      const int x = cell - row * g.nx;
+      const int row = cell / g.px;
+      const int x = cell - row * g.px;
       const int z = row / g.ny;
       const int y = row - z * g.ny;
       lo_x = g.zg_x && x == 0;
@@ -668,7 +680,7 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
       for (int k = 0; k < 5; ++k) vals[3 + k] = d.dq[k];
       vals[8] = d.nonfinite;
     }
-    if constexpr (SRC) add_source(f, src, (int64_t)g.nx * g.ny * g.nz, b.n);
+    if constexpr (SRC) add_source(f, src, g, x, y, z);
     // FP16 dither keys of the destination cells (the x slots are keyed by the cell
     // that finally stores them, which is their destination as well)
     uint32_t hn = 0u, hyp = 0u, hym = 0u, hzp = 0u, hzm = 0u;

@@ -31,31 +31,32 @@ struct CellPos {
   bool active;
 };
 
-// Block b holds the consecutive cells [b * blockDim.x, (b + 1) * blockDim.x), so
-// every lane but those past the last cell has a cell and a wave reads and writes
-// 64 consecutive elements of each array.  (Blocks that stopped at row ends left
-// lanes idle and waves straddling cache lines whenever nx was not a multiple of
-// the block: 144-cell rows kept 144 of 256 lanes busy and cost a fifth of the
-// rate.)  When whole blocks fit a row the position comes from the block index
-// alone; otherwise each lane divides its cell index.
+// Block b holds the consecutive elements [b * blockDim.x, (b + 1) * blockDim.x) of
+// the arrays, so a wave reads and writes 64 consecutive elements of each array;
+// lanes past the last row or in a row's padding (x >= nx) have no cell.  (Blocks
+// that stopped at row ends left lanes idle and waves straddling cache lines
+// whenever nx was not a multiple of the block: 144-cell rows kept 144 of 256 lanes
+// busy and cost a fifth of the rate.)  When whole blocks fit a row the position
+// comes from the block index alone; otherwise each lane divides its element index.
 __device__ __forceinline__ CellPos block_cell(const Grid& g) {
   const int bx = blockDim.x;
   const int b = blockIdx.x;
   CellPos p;
-  if (g.nx % bx == 0) {
-    const int nxb = g.nx / bx;
+  if (g.px % bx == 0) {
+    const int nxb = g.px / bx;
     const int row = b / nxb;
     p.x = (b - row * nxb) * bx + threadIdx.x;
     p.y = row % g.ny;
     p.z = row / g.ny;
-    p.active = row < g.ny * g.nz;
+    p.active = row < g.ny * g.nz && p.x < g.nx;
   } else {
-    const int n = b * bx + (int)threadIdx.x;  // below 2^31: the cell count is capped
-    p.active = n < g.nx * g.ny * g.nz;
-    const int row = p.active ? n / g.nx : 0;
-    p.x = p.active ? n - row * g.nx : 0;
+    const int n = b * bx + (int)threadIdx.x;  // below 2^31: the element count is capped
+    const bool in = n < g.px * g.ny * g.nz;
+    const int row = in ? n / g.px : 0;
+    p.x = in ? n - row * g.px : 0;
     p.z = row / g.ny;
     p.y = row - p.z * g.ny;
+    p.active = in && p.x < g.nx;
   }
   return p;
 }
@@ -115,7 +116,8 @@ __global__ void __launch_bounds__(256) k_step_even_pairs(_Float16* __restrict__ 
 #pragma unroll
     for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
   }
-  if (n < g.nx * g.ny * g.nz) pair_update_even<COLL, ZG, DIAG, NT>(F, g, c, n, vals, skey);
+  // nx and px even: a pair lies wholly in a row or wholly in its padding
+  if (n < g.px * g.ny * g.nz && n % g.px < g.nx) pair_update_even<COLL, ZG, DIAG, NT>(F, g, c, n, vals, skey);
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid
   bool act;
   if constexpr (ROWS) {
     const int row = (int)blockIdx.x;
-    n0 = row * g.nx;
+    n0 = row * g.px;
     act = (int)threadIdx.x < g.nx;
     z = row / g.ny;
     y = row - z * g.ny;
@@ -141,12 +143,13 @@ __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid
   } else {
     n0 = (int)blockIdx.x * (int)blockDim.x;
     const int n = n0 + (int)threadIdx.x;
-    act = n < g.nx * g.ny * g.nz;
+    act = n < g.px * g.ny * g.nz;
     if (act) {
-      const int row = n / g.nx;
-      x = n - row * g.nx;
+      const int row = n / g.px;
+      x = n - row * g.px;
       z = row / g.ny;
       y = row - z * g.ny;
+      act = x < g.nx;  // the row's padding holds no cell
     }
   }
   float vals[kDiagVals];
@@ -238,6 +241,7 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
   const int y = (int)(row % g.ny);
   const int z = (int)(row / g.ny);
   const int64_t plane = (int64_t)g.nx * g.ny;
+  const int64_t ns = x + (int64_t)g.px * row;  // the cell's element in the padded rows
   const int64_t xm = fd_neighbour(n, x, -1, g.nx, g.zg_x, 1), xp = fd_neighbour(n, x, 1, g.nx, g.zg_x, 1);
   const int64_t ym = fd_neighbour(n, y, -1, g.ny, g.zg_y, g.nx), yp = fd_neighbour(n, y, 1, g.ny, g.zg_y, g.nx);
   const int64_t zm = fd_neighbour(n, z, -1, g.nz, g.zg_z, plane), zp = fd_neighbour(n, z, 1, g.nz, g.zg_z, plane);
@@ -296,7 +300,7 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
       for (int i = 0; i < kQ; ++i) m = fmaxf(m, fabsf(v[i]));
       field_max(maxabs, k, m);
     } else {
-      T* Fk = F + (int64_t)(7 * k) * g.S + n;
+      T* Fk = F + (int64_t)(7 * k) * g.S + ns;
       for (int i = 0; i < kQ; ++i) Fk[(int64_t)i * g.S] = static_cast<T>(v[i] * c.sc[k]);
     }
   }
@@ -453,9 +457,7 @@ hipError_t launch_step(const StepLaunch& L, hipStream_t s) {
   return L.src ? dispatch_t<float, true>(L, s) : dispatch_t<float, false>(L, s);
 }
 
-int64_t step_blocks(const Grid& g, int block) {
-  return ((int64_t)g.nx * g.ny * g.nz + block - 1) / block;
-}
+int64_t step_blocks(const Grid& g, int block) { return (row_cells(g) + block - 1) / block; }
 
 // Launch shape of k_step_odd_tiles: one block per x-row when a row fits in a block
 // (no index division, no tile edge inside a row), else linear tiles.  The dynamic
@@ -469,7 +471,7 @@ OddTiles odd_tiles(const Grid& g, bool f16) {
   t.rows = g.nx <= kMaxRowTile && g.nx % (f16 ? kRowMultipleF16 : kRowMultipleF32) == 0;
   const int tile = f16 ? kOddTileF16 : kOddTileF32;
   t.block = t.rows ? (g.nx + 63) / 64 * 64 : tile;
-  t.blocks = t.rows ? (int64_t)g.ny * g.nz : ((int64_t)g.nx * g.ny * g.nz + tile - 1) / tile;
+  t.blocks = t.rows ? (int64_t)g.ny * g.nz : (row_cells(g) + tile - 1) / tile;
   const int waves = (t.rows && !f16) ? 8 : 16;
   const int need = 15 * (int)sizeof(float) * t.block;
   const int per_cu = waves * 64 / t.block > 1 ? waves * 64 / t.block : 1;
@@ -483,7 +485,8 @@ bool even_pairs(const StepLaunch& L) {
   // measured: +3% at 256^3 and +4% at 384^3, but -8% at 128^3 (its two cells per
   // lane take about 190 registers, so fewer waves hide the latency)
   const int64_t N = (int64_t)L.g.nx * L.g.ny * L.g.nz;
-  return !L.odd && L.f16 && !L.src && L.block <= 256 && N % 2 == 0 && N >= kPairMinCells;
+  return !L.odd && L.f16 && !L.src && L.block <= 256 && L.g.nx % 2 == 0 && L.g.px % 2 == 0 &&
+         N >= kPairMinCells;
 }
 
 bool odd_pairs(const StepLaunch& L) {
@@ -499,7 +502,7 @@ bool odd_pairs(const StepLaunch& L) {
 int odd_pair_lds(const Grid& g) { return 15 * (int)sizeof(float) * g.nx; }
 
 int64_t pair_blocks(const StepLaunch& L) {
-  const int64_t pairs = (int64_t)L.g.nx * L.g.ny * L.g.nz / 2;
+  const int64_t pairs = row_cells(L.g) / 2;
   return (pairs + L.block - 1) / L.block;
 }
 

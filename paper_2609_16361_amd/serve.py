@@ -96,12 +96,18 @@ class ServeStats:
 
 
 def state_bytes(params: dict, storage: int) -> int:
-    """Device bytes of one instance (35 arrays padded to 256 B) -- mirrors
-    lbm_state_bytes without a device call."""
-    n = int(params["nx"]) * int(params["ny"]) * int(params["nz"])
+    """Device bytes of one instance -- mirrors lbm_state_bytes without a device
+    call: 35 arrays, each starting on a 256-byte boundary, whose x-rows are padded
+    to whole 128-byte lines when that adds at most an eighth of the row."""
+    nx, ny, nz = int(params["nx"]), int(params["ny"]), int(params["nz"])
     el = 2 if storage else 4
+    px = nx
+    if ny * nz > 1:
+        line = 128 // el
+        pr = (nx + line - 1) // line * line
+        px = pr if 8 * (pr - nx) <= nx and pr * ny * nz <= 2 ** 31 - 1 - 65535 else nx
     align = 256 // el
-    s = (n + int(params.get("layout_pad", 0)) + align - 1) // align * align
+    s = (px * ny * nz + int(params.get("layout_pad", 0)) + align - 1) // align * align
     return 35 * el * s
 
 

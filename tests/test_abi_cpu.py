@@ -105,11 +105,20 @@ def test_state_bytes():
     assert binding.lbm_state_bytes(p16) == 35 * 2 * n
     small = binding.make_params(inputs.sod(n=100, ny=3, nz=1).params)
     per = (300 + 63) // 64 * 64                      # arrays padded to 256 bytes
-    assert binding.lbm_state_bytes(small) == 35 * 4 * per
+    assert binding.lbm_state_bytes(small) == 35 * 4 * per   # 28 of 100 would be too much row padding
+    # rows padded to whole 128-byte lines when that adds at most an eighth: 144 -> 160
+    # cells in FP32; in FP16 (64-cell lines) 144 -> 192 would add a third, so none
+    odd = binding.make_params(inputs.tgv(n=144, dims=(144, 144, 144)).params)
+    assert binding.lbm_state_bytes(odd) == 35 * 4 * ((160 * 144 * 144 + 63) // 64 * 64)
+    odd.storage = binding.LBM_STORE_F16
+    assert binding.lbm_state_bytes(odd) == 35 * 2 * ((144 ** 3 + 127) // 128 * 128)
+    one_row = binding.make_params(inputs.sod(n=1000, ny=1, nz=1).params)   # nothing to align
+    assert binding.lbm_state_bytes(one_row) == 35 * 4 * ((1000 + 63) // 64 * 64)
     small.layout_pad = 1000
     assert binding.lbm_state_bytes(small) == 35 * 4 * ((1300 + 63) // 64 * 64)
     # one MI355X holds a 1024^3 FP32 state (150 GB of its 288 GB); 32-bit cell
-    # indices allow up to 2^31 - 2^16 cells
+    # indices allow up to 2^31 - 2^16 cells (1290^3 keeps unpadded rows: padded to
+    # 1312 they would leave that range)
     big = binding.make_params(inputs.tgv(n=8, dims=(8, 8, 8)).params)
     big.nx = big.ny = big.nz = 1024
     assert binding.lbm_state_bytes(big) == 35 * 4 * 1024 ** 3
