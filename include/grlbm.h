@@ -56,6 +56,12 @@ typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_ZERO_GRADIENT = 1 } lbm_bc;
  * for the shock cases, BGK for smooth ones. */
 typedef enum { LBM_COLL_RLB_SENSOR = 0, LBM_COLL_BGK = 1 } lbm_collision;
 typedef enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1 } lbm_storage;
+/* Initial populations (the paper states none).  FIRST_ORDER: the first moment the
+ * update holds a resolved field at, from central differences of the initial fields
+ * (lbm_init_fields); EQUILIBRIUM: the equilibrium of the fields with their advective
+ * flux, for initial data with jumps (a Riemann problem), where differences across a
+ * jump are no gradient and would start negative densities. */
+typedef enum { LBM_START_FIRST_ORDER = 0, LBM_START_EQUILIBRIUM = 1 } lbm_start;
 /* Listing 1: mu(T) = mu_ref (1+T_S) (T/T_ref)^(3/2) / (T/T_ref + T_S). */
 typedef enum { LBM_MU_CONSTANT = 0, LBM_MU_SUTHERLAND = 1 } lbm_mu_law;
 
@@ -67,6 +73,7 @@ typedef struct {
   int32_t mu_law;              /* lbm_mu_law                                           */
   int32_t layout_pad;          /* extra elements between population arrays (>= 0);
                                   arrays always start on 256-byte boundaries          */
+  int32_t start;               /* lbm_start: how the initial fields become populations */
   double gamma;                /* ratio of specific heats (eq. 2 equation of state)    */
   double mu_ref, kappa_ref;    /* viscosity and conductivity at T_ref; both scale with
                                   the same law: mu = mu_ref r(T), kappa = kappa_ref r(T),
@@ -118,15 +125,17 @@ lbm_status lbm_create_in(const lbm_params* p, void* dev_buf, size_t bytes, void*
                          lbm_ctx** out);
 
 /* Set the state from the conserved fields Q and reset the step counter to 0.  The
- * paper states no initialisation; the populations get zeroth moment Q, the
- * equilibrium second moment and the first moment J_k = Phi_k - (c_s^2/omega_k)
- * grad Q_k that the update holds a smooth field at to first order (the fixed point
- * of the relaxation of the first moment followed by streaming), with grad Q from
- * central differences of Q (periodic wrap; beyond a zero-gradient face the cell
- * itself) and Phi the flux of eq. 2 with the Newtonian stress and Fourier flux of
- * that gradient.  The reconstruction of eq. 4 returns that gradient at step 0, and
- * no step-to-step oscillation of the non-equilibrium is started (omega -> 2 would
- * leave it undamped).  A uniform state starts at its equilibrium.  Q: host array
+ * paper states no initialisation.  With params.start = LBM_START_FIRST_ORDER the
+ * populations get zeroth moment Q, the equilibrium second moment and the first
+ * moment J_k = Phi_k - (c_s^2/omega_k) grad Q_k that the update holds a resolved
+ * field at to first order (the fixed point of the relaxation of the first moment
+ * followed by streaming), with grad Q from central differences of Q (periodic wrap;
+ * beyond a zero-gradient face the cell itself) and Phi the flux of eq. 2 with the
+ * Newtonian stress and Fourier flux of that gradient.  The reconstruction of eq. 4
+ * returns that gradient at step 0, and no step-to-step oscillation of the
+ * non-equilibrium is started (omega -> 2 would leave it undamped).  With
+ * LBM_START_EQUILIBRIUM they are the equilibrium of Q with the advective flux.  A
+ * uniform state starts at its equilibrium either way.  Q: host array
  * [5][nz][ny][nx] of doubles, lattice units, field order (rho, rho u_x, rho u_y,
  * rho u_z, E).  EINVAL (state unchanged) if a value is not finite or the density
  * or the pressure (gamma - 1)(E - |rho u|^2 / (2 rho)) of a cell is not positive.

@@ -9,7 +9,8 @@ buffers, push streaming).  This module only marshals numpy arrays.
 
 Parameters are passed as a plain dict in lattice units with the keys
   nx, ny, nz, bc (3 ints: 0 periodic, 1 zero gradient), collision (0 regularized
-  with sensor, 1 BGK), mu_law (0 constant, 1 Sutherland), gamma, mu_ref, kappa_ref,
+  with sensor, 1 BGK), mu_law (0 constant, 1 Sutherland), start (0 first-order,
+  1 equilibrium; optional, default 0), gamma, mu_ref, kappa_ref,
   T_ref, T_S, omega (5 floats), sensor_gain, J_min, omega_min, rho_min, p_min.
 Extra keys are ignored.
 """
@@ -27,7 +28,7 @@ class OraParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 3),
-        ("collision", ctypes.c_int32), ("mu_law", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("mu_law", ctypes.c_int32), ("start", ctypes.c_int32),
         ("gamma", ctypes.c_double),
         ("mu_ref", ctypes.c_double), ("kappa_ref", ctypes.c_double),
         ("T_ref", ctypes.c_double), ("T_S", ctypes.c_double),
@@ -108,6 +109,7 @@ def make_params(p: dict) -> OraParams:
         o.bc[a] = int(p["bc"][a])
     o.collision = int(p["collision"])
     o.mu_law = int(p["mu_law"])
+    o.start = int(p.get("start", 0))
     o.gamma = float(p["gamma"])
     o.mu_ref = float(p["mu_ref"])
     o.kappa_ref = float(p["kappa_ref"])

@@ -71,6 +71,7 @@ typedef struct {
   int32_t bc[3];       /* 0 = periodic, 1 = zero gradient                         */
   int32_t collision;   /* 0 = regularized with compression sensor, 1 = BGK        */
   int32_t mu_law;      /* 0 = constant mu, 1 = Sutherland                         */
+  int32_t start;       /* 0 = first-order start, 1 = equilibrium start (ora_init)  */
   double gamma;
   double mu_ref, kappa_ref, T_ref, T_S;
   double omega[ORA_NF];
@@ -379,7 +380,9 @@ static int ora_fd_nb(int x, int d, int n, int bc) {
  * f_i = w_i (Q + c_i . J / c_s^2).  The reconstruction of eq. 4 then returns that
  * grad Q at step 0, and no odd-even start-up oscillation of the non-equilibrium is
  * excited (at omega -> 2 it would not decay).  A uniform state gets f = f_eq.
- * Q[5][N] -> f[35][N]. */
+ * With P->start = 1 (initial data with jumps, where a difference across the jump is
+ * no gradient: a Riemann problem) the start is the equilibrium of Q with the
+ * advective flux.  Q[5][N] -> f[35][N]. */
 void ora_init(const ora_params* P, const double* Q, double* f) {
   const int nx = P->nx, ny = P->ny, nz = P->nz;
   const int64_t N = ora_cells(P);
@@ -402,6 +405,7 @@ void ora_init(const ora_params* P, const double* Q, double* f) {
           G[k][0] = 0.5 * (Q[k * N + xp] - Q[k * N + xm]);
           G[k][1] = 0.5 * (Q[k * N + yp] - Q[k * N + ym]);
           G[k][2] = 0.5 * (Q[k * N + zp] - Q[k * N + zm]);
+          if (P->start == 1) G[k][0] = G[k][1] = G[k][2] = 0.0;
         }
         const double ratio = ora_mu_ratio(P, T);
         ora_assemble_M(P, rf, u, T, P->mu_ref * ratio, P->kappa_ref * ratio, M);

@@ -22,6 +22,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_ESTATE = 0, -1, 
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
                 -4: "LBM_EDIVERGED", -5: "LBM_ESTATE"}
 LBM_STORE_F32, LBM_STORE_F16 = 0, 1
+LBM_START_FIRST_ORDER, LBM_START_EQUILIBRIUM = 0, 1
 
 
 class lbm_params(ctypes.Structure):
@@ -29,7 +30,7 @@ class lbm_params(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("bc", ctypes.c_int32 * 3),
         ("collision", ctypes.c_int32), ("storage", ctypes.c_int32), ("mu_law", ctypes.c_int32),
-        ("layout_pad", ctypes.c_int32),
+        ("layout_pad", ctypes.c_int32), ("start", ctypes.c_int32),
         ("gamma", ctypes.c_double),
         ("mu_ref", ctypes.c_double), ("kappa_ref", ctypes.c_double),
         ("T_ref", ctypes.c_double), ("T_S", ctypes.c_double),
@@ -176,6 +177,7 @@ def make_params(p: dict, storage: int | None = None, layout_pad: int = 0) -> lbm
     o.storage = int(p.get("storage", LBM_STORE_F32) if storage is None else storage)
     o.mu_law = int(p["mu_law"])
     o.layout_pad = int(p.get("layout_pad", layout_pad))
+    o.start = int(p.get("start", LBM_START_FIRST_ORDER))
     o.gamma = float(p["gamma"])
     o.mu_ref = float(p["mu_ref"])
     o.kappa_ref = float(p["kappa_ref"])

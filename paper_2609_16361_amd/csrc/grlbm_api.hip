@@ -60,6 +60,8 @@ lbm_status validate(const lbm_params* p) {
   if (p->mu_law != LBM_MU_CONSTANT && p->mu_law != LBM_MU_SUTHERLAND)
     return fail(LBM_EINVAL, "mu_law = %d is not an lbm_mu_law", p->mu_law);
   if (p->layout_pad < 0) return fail(LBM_EINVAL, "layout_pad must be >= 0");
+  if (p->start != LBM_START_FIRST_ORDER && p->start != LBM_START_EQUILIBRIUM)
+    return fail(LBM_EINVAL, "start = %d is not an lbm_start", p->start);
   if (!finite_pos(p->gamma - 1.0)) return fail(LBM_EINVAL, "gamma must be finite and > 1");
   if (!(std::isfinite(p->mu_ref) && p->mu_ref >= 0.0)) return fail(LBM_EINVAL, "mu_ref must be >= 0");
   if (!(std::isfinite(p->kappa_ref) && p->kappa_ref >= 0.0))
@@ -189,6 +191,7 @@ InitCoef make_init_coef(const lbm_params* p) {
   ic.E_ref = p->E_ref;
   for (int k = 0; k < 5; ++k) ic.inv_omega[k] = 1.0 / p->omega[k];
   ic.sutherland = p->mu_law == LBM_MU_SUTHERLAND ? 1 : 0;
+  ic.equilibrium = p->start == LBM_START_EQUILIBRIUM ? 1 : 0;
   return ic;
 }
 

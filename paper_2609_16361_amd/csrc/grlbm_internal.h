@@ -36,6 +36,7 @@ struct InitCoef {
   double rho_min, p_min, rho_ref, E_ref;
   double inv_omega[5];
   int32_t sutherland;
+  int32_t equilibrium;  // 1: the equilibrium with the advective flux (LBM_START_EQUILIBRIUM)
 };
 InitCoef make_init_coef(const lbm_params* p);
 

@@ -228,8 +228,10 @@ __device__ __forceinline__ int64_t fd_neighbour(int64_t n, int x, int d, int len
 // the non-equilibrium part the first streaming leaves J - Phi = -c_s^2 grad Q, omega
 // times too large, and the difference oscillates from step to step undamped as
 // omega -> 2.  Computed in FP64, stored as g_i = w_i (Q - Q_ref + 4 c_i . J) times
-// the field's storage scale.  With maxabs set, nothing is stored and the largest |g|
-// of each field is reduced instead (used to pick the FP16 scales).
+// the field's storage scale.  With ic.equilibrium (initial data with jumps, where a
+// difference across a jump is no gradient) grad Q is taken as zero, which leaves
+// the equilibrium of Q with the advective flux.  With maxabs set, nothing is stored
+// and the largest |g| of each field is reduced instead (used to pick the FP16 scales).
 template <typename T>
 __global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c, InitCoef ic,
                                                const double* __restrict__ Q, int64_t N,
@@ -249,9 +251,10 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
   for (int k = 0; k < 5; ++k) {
     const double* Qk = Q + k * N;
     q[k] = Qk[n];
-    G[k][0] = 0.5 * (Qk[xp] - Qk[xm]);
-    G[k][1] = 0.5 * (Qk[yp] - Qk[ym]);
-    G[k][2] = 0.5 * (Qk[zp] - Qk[zm]);
+    // the equilibrium start (data with jumps) takes no gradient
+    G[k][0] = ic.equilibrium ? 0.0 : 0.5 * (Qk[xp] - Qk[xm]);
+    G[k][1] = ic.equilibrium ? 0.0 : 0.5 * (Qk[yp] - Qk[ym]);
+    G[k][2] = ic.equilibrium ? 0.0 : 0.5 * (Qk[zp] - Qk[zm]);
   }
   const double rf = fmax(q[0], ic.rho_min);
   const double u[3] = {q[1] / rf, q[2] / rf, q[3] / rf};

@@ -18,7 +18,9 @@ Parameter dict keys (lattice units): nx, ny, nz, bc (per axis, 0 periodic, 1 zer
 gradient), collision (0 regularized with sensor, 1 BGK), mu_law (0 constant,
 1 Sutherland), gamma, mu_ref, kappa_ref, T_ref, T_S, omega[5], sensor_gain, J_min,
 omega_min, rho_min, p_min, rho_ref, E_ref (the uniform reference state whose
-equilibrium the stored populations are shifted by, Sec. 2.2).
+equilibrium the stored populations are shifted by, Sec. 2.2), and optionally start
+(0 first-order start from the initial gradients, 1 equilibrium start for data with
+jumps; the Sod tubes use 1).
 """
 from __future__ import annotations
 
@@ -30,6 +32,7 @@ import numpy as np
 T_SUTHERLAND = 0.4042  # Listing 1
 PERIODIC, ZERO_GRADIENT = 0, 1
 RLB_SENSOR, BGK = 0, 1
+START_FIRST_ORDER, START_EQUILIBRIUM = 0, 1
 MU_CONSTANT, MU_SUTHERLAND = 0, 1
 
 
@@ -189,6 +192,7 @@ def sod(n=256, ny=4, nz=4, r=None, t_end=0.2, steps=None, left=(1.0, 1.0), right
                       mu=mu * r / dx, Pr=Pr, omega=omega, sensor_gain=sensor_gain,
                       J_min=J_min, omega_min=omega_min, p_min=1e-4 * r * r,
                       rho_ref=right[0], E_ref=right[1] * r * r / (gamma - 1.0))
+    prm["start"] = START_EQUILIBRIUM  # Riemann data: no gradient across the jump
     if steps is None:
         steps = int(round(t_end / (r * dx)))
     return Case("sod", prm, Q, int(steps), 0,

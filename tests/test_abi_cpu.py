@@ -138,6 +138,7 @@ def test_state_bytes():
     (lambda p: setattr(p, "storage", 9), "storage"),
     (lambda p: setattr(p, "rho_min", 0.0), "rho_min"),
     (lambda p: setattr(p, "layout_pad", -1), "layout_pad"),
+    (lambda p: setattr(p, "start", 2), "start"),
     (lambda p: setattr(p, "T_ref", float("nan")), "T_ref"),
     (lambda p: (setattr(p, "nx", 1291), setattr(p, "ny", 1291), setattr(p, "nz", 1291)), "32-bit"),
 ])
