@@ -303,6 +303,13 @@ def bench_spectral(stream, n=128, tc_samples=(1.0, 2.0, 3.0, 4.0, 5.0)):
     return {"workload": f"compressible Taylor-Green {n}^3", "samples": rows}
 
 
+# Kinds whose FP16-served results meet the 1e-2 bar against FP32 (relative L2 of
+# rho, rho u, E).  Vortices run near omega = 2, where the regularized collision
+# amplifies FP16 rounding (measured 0.10 median, 0.52 worst on the 64-request
+# mix); they are served in FP32.
+FP16_KINDS = ("sod", "becker")
+
+
 def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9, chunk=50,
                 max_active_cells=8 * 2 ** 20):
     """Serving mix (Poisson arrivals at `rate`, 40% Sod variants, 40% Taylor-Green,
@@ -322,7 +329,11 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
                         "library (LBM_EINVAL) in every leg and counted as rejected",
            "offered_glup": work / 1e9,
            "mix": {k: sum(1 for r in trace if r.kind == k) for k in ("sod", "tgv", "becker")},
-           "fp16_share": sum(r.storage for r in trace) / count}
+           "fp16_share": sum(r.storage for r in trace) / count,
+           "fp16_served": {"kinds": list(FP16_KINDS),
+                           "requests": sum(1 for r in trace if r.storage and r.kind in FP16_KINDS),
+                           "note": "FP16 requested by vortices is served in FP32: near omega = 2 their FP16 "
+                                   "results miss the 1e-2 bar against FP32"}}
 
     failures = {}
     progress = {"leg": "", "done": 0}  # long traces report every 100 results on stderr
@@ -347,7 +358,7 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
 
     def keep_f16(req, Q):
         ok = finite(req, Q)
-        if ok and req.storage == binding.LBM_STORE_F16:
+        if ok and req.storage == binding.LBM_STORE_F16 and req.kind in FP16_KINDS:
             f16_results[req.rid] = Q.astype(np.float32)
         return ok
 
@@ -369,7 +380,7 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
                            stream=stream.cuda_stream) as b:
             srv = serve.Server(b, arena_bytes=budget_bytes, chunk_steps=chunk, result_handler=handler,
                                sync=torch.cuda.synchronize, max_active_cells=max_active_cells,
-                               storage_override=storage_override,
+                               storage_override=storage_override, fp16_kinds=FP16_KINDS,
                                failure_handler=lambda req: finished(req, False))
             return srv.serve(trace)
 
@@ -382,9 +393,11 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
     out["failures"] = failures
     out["batched_fp32"] = batched(binding.LBM_STORE_F32, compare_f32).summary()
     out["accuracy"] = {
+        "bar": "max over rho, rho u, E of the relative L2 against the FP32 result of the same request <= 1e-2",
         "batched_fp32_vs_sequential_fp32": "bitwise equal (same kernels and arithmetic per instance)",
         "fp16_vs_fp32_max_rel_l2": {k: {"requests": len(v), "median": float(np.median(v)), "max": float(np.max(v))}
-                                    for k, v in sorted(f16_err.items())}}
+                                    for k, v in sorted(f16_err.items())},
+        "fp16_served_within_bar": bool(all(max(v) <= 1e-2 for v in f16_err.values()))}
 
     def fp32_solver(params):
         return binding.Solver(params, stream=stream.cuda_stream)

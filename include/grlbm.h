@@ -19,8 +19,8 @@
  * Storage.  One device buffer holds 35 population arrays (structure of arrays,
  * x fastest), updated in place with the AA access pattern, so a single copy of the
  * state suffices: 140 bytes per cell in FP32, 70 in FP16.  On grids of more than
- * one x-row, each row is padded to whole 128-byte lines when that adds at most an
- * eighth of its length (and keeps the padded grid in the 32-bit index range), so
+ * one x-row, each row is padded to whole 128-byte lines when that adds at most a
+ * sixteenth of its length (and keeps the padded grid in the 32-bit index range), so
  * that the rows a cell's +-y and +-z neighbours sit in start on a line too; the
  * padding is never read or written.  lbm_state_bytes accounts for it.  The stored value is the
  * deviation f - w_i Q_ref from the equilibrium of a uniform reference state

@@ -102,14 +102,14 @@ lbm_status check_fields(const lbm_params* p, const double* Q) {
 }
 
 int64_t row_pitch(const lbm_params* p) {
-  // rows padded to whole 128-byte lines when the padding is at most an eighth of
+  // rows padded to whole 128-byte lines when the padding is at most a sixteenth of
   // the row (a grid of one row has no +-y or +-z neighbours to align) ...
   const int64_t nx = p->nx;
   if ((int64_t)p->ny * p->nz == 1) return nx;
   const int64_t line = p->storage == LBM_STORE_F16 ? 64 : 32;
   const int64_t px = (nx + line - 1) / line * line;
   // ... and never where the padding alone would leave the 32-bit index range
-  if (8 * (px - nx) > nx || px * p->ny * p->nz > (int64_t)INT32_MAX - 65535) return nx;
+  if (16 * (px - nx) > nx || px * p->ny * p->nz > (int64_t)INT32_MAX - 65535) return nx;
   return px;
 }
 

@@ -6,7 +6,7 @@
 // (rho, rho u_x, rho u_y, rho u_z, E) and D3Q7 direction i (0, +x, -x, +y, -y, +z,
 // -z); array s starts at element s * S, and cell (x, y, z) sits at element
 // x + px (y + ny z) of every array, where the row pitch px >= nx pads each x-row to
-// a whole number of 128-byte lines when that costs at most an eighth of the row
+// a whole number of 128-byte lines when that costs at most a sixteenth of the row
 // (so the +-y and +-z neighbours of an aligned run of cells are aligned runs too);
 // elements x in [nx, px) are padding that no update reads or writes.  Each stored
 // value is g = f - w_i Q_ref,k.

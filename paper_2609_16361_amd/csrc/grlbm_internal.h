@@ -23,7 +23,7 @@ lbm_status validate(const lbm_params* p);
 // that is not.
 lbm_status check_fields(const lbm_params* p, const double* Q);
 // Elements between consecutive x-rows: nx, or nx rounded up to whole 128-byte
-// lines when that adds at most an eighth of the row (grids of more than one row).
+// lines when that adds at most a sixteenth of the row (grids of more than one row).
 int64_t row_pitch(const lbm_params* p);
 int64_t slot_stride(const lbm_params* p);
 size_t state_bytes(const lbm_params* p);

@@ -98,14 +98,14 @@ class ServeStats:
 def state_bytes(params: dict, storage: int) -> int:
     """Device bytes of one instance -- mirrors lbm_state_bytes without a device
     call: 35 arrays, each starting on a 256-byte boundary, whose x-rows are padded
-    to whole 128-byte lines when that adds at most an eighth of the row."""
+    to whole 128-byte lines when that adds at most a sixteenth of the row."""
     nx, ny, nz = int(params["nx"]), int(params["ny"]), int(params["nz"])
     el = 2 if storage else 4
     px = nx
     if ny * nz > 1:
         line = 128 // el
         pr = (nx + line - 1) // line * line
-        px = pr if 8 * (pr - nx) <= nx and pr * ny * nz <= 2 ** 31 - 1 - 65535 else nx
+        px = pr if 16 * (pr - nx) <= nx and pr * ny * nz <= 2 ** 31 - 1 - 65535 else nx
     align = 256 // el
     s = (px * ny * nz + int(params.get("layout_pad", 0)) + align - 1) // align * align
     return 35 * el * s
@@ -126,7 +126,7 @@ class Server:
                  chunk_steps: int = 50, result_handler=None, clock=time.perf_counter,
                  sync=None, max_instances: int = 4096, storage_override: int | None = None,
                  order: str = "largest", max_wait_s: float | None = 2.0, stop_diverged: bool = True,
-                 check_steps: int = 200, failure_handler=None):
+                 check_steps: int = 200, failure_handler=None, fp16_kinds=None):
         self.b = backend
         self.arena_bytes = int(arena_bytes)
         self.max_cells = max_active_cells
@@ -137,6 +137,9 @@ class Server:
         self.max_instances = max_instances
         # None: each request's own storage; else every request in this storage
         self.storage_override = storage_override
+        # None: FP16 wherever requested; else a request of a kind outside this set
+        # runs in FP32 (kinds whose stated accuracy FP16 storage does not reach)
+        self.fp16_kinds = None if fp16_kinds is None else set(fp16_kinds)
         # "fifo": admit arrived requests in arrival order, the first that does not
         # fit blocks the rest; "largest": among the arrived requests, largest work
         # (cells x steps) first, skipping those that do not fit yet, except that
@@ -153,6 +156,14 @@ class Server:
         self.check_chunks = max(1, -(-int(check_steps) // self.chunk))
         self.on_failure = failure_handler
 
+    def storage_of(self, r) -> int:
+        """The storage a request runs in."""
+        if self.storage_override is not None:
+            return self.storage_override
+        if r.storage and self.fp16_kinds is not None and r.kind not in self.fp16_kinds:
+            return 0
+        return r.storage
+
     @staticmethod
     def _reject(o: Outcome, now: float, why: str) -> None:
         o.ok = False
@@ -161,7 +172,7 @@ class Server:
 
     def serve(self, requests) -> ServeStats:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        stg = {r.rid: (r.storage if self.storage_override is None else self.storage_override) for r in reqs}
+        stg = {r.rid: self.storage_of(r) for r in reqs}
         out = {r.rid: Outcome(r.rid, r.kind, stg[r.rid], r.case.cells, r.steps, r.arrival) for r in reqs}
         pending = list(reqs)
         active = {}                 # instance id -> (request, bytes)

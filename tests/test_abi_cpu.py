@@ -106,12 +106,14 @@ def test_state_bytes():
     small = binding.make_params(inputs.sod(n=100, ny=3, nz=1).params)
     per = (300 + 63) // 64 * 64                      # arrays padded to 256 bytes
     assert binding.lbm_state_bytes(small) == 35 * 4 * per   # 28 of 100 would be too much row padding
-    # rows padded to whole 128-byte lines when that adds at most an eighth: 144 -> 160
-    # cells in FP32; in FP16 (64-cell lines) 144 -> 192 would add a third, so none
-    odd = binding.make_params(inputs.tgv(n=144, dims=(144, 144, 144)).params)
-    assert binding.lbm_state_bytes(odd) == 35 * 4 * ((160 * 144 * 144 + 63) // 64 * 64)
+    # rows padded to whole 128-byte lines when that adds at most a sixteenth: a
+    # 1000-cell row to 1024 in FP32 and FP16; 144 -> 160 would add a ninth, so none
+    odd = binding.make_params(inputs.tgv(n=144, dims=(1000, 12, 10)).params)
+    assert binding.lbm_state_bytes(odd) == 35 * 4 * ((1024 * 120 + 63) // 64 * 64)
     odd.storage = binding.LBM_STORE_F16
-    assert binding.lbm_state_bytes(odd) == 35 * 2 * ((144 ** 3 + 127) // 128 * 128)
+    assert binding.lbm_state_bytes(odd) == 35 * 2 * ((1024 * 120 + 127) // 128 * 128)
+    cube = binding.make_params(inputs.tgv(n=144, dims=(144, 144, 144)).params)
+    assert binding.lbm_state_bytes(cube) == 35 * 4 * ((144 ** 3 + 63) // 64 * 64)
     one_row = binding.make_params(inputs.sod(n=1000, ny=1, nz=1).params)   # nothing to align
     assert binding.lbm_state_bytes(one_row) == 35 * 4 * ((1000 + 63) // 64 * 64)
     small.layout_pad = 1000

@@ -381,3 +381,25 @@ def test_state_bytes_mirrors_the_library():
             p = binding.make_params(params)
             p.storage = storage
             assert serve.state_bytes(params, storage) == binding.lbm_state_bytes(p), (nx, ny, nz, pad, storage)
+
+
+def test_fp16_only_for_the_allowed_kinds():
+    """With fp16_kinds a request asking for FP16 storage runs in it only when its kind
+    is in the set; the others run in FP32."""
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    seen = []
+    add = fb.add
+
+    def spy(params, Q, steps, storage=0):
+        seen.append((steps, storage))
+        return add(params, Q, steps, storage)
+
+    fb.add = spy
+    reqs = [make_req(0, 0.0, 320, 10, storage=1), make_req(1, 0.0, 320, 20, storage=1),
+            make_req(2, 0.0, 320, 30, storage=0)]
+    reqs[1].kind = "tgv"
+    srv = serve.Server(fb, arena_bytes=1 << 30, chunk_steps=10, clock=clk, order="fifo", fp16_kinds={"x"})
+    st = srv.serve(reqs)
+    assert sorted(seen) == [(10, 1), (20, 0), (30, 0)]
+    assert [o.storage for o in st.outcomes] == [1, 0, 0]
