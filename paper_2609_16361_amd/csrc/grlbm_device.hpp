@@ -108,6 +108,54 @@ __device__ __forceinline__ int64_t odd_src(const Grid& g, const Nbr& b, int i) {
   }
 }
 
+// Element `cell` of the array at `base`; `base` must hold the same value in every
+// lane of the wave (every caller passes a slot array of the kernel's state or of
+// the block's batch instance).  FP16: the byte offset is formed in 32 bits (a cell
+// index below 2^31 gives one below 2^32) and added to the base held in scalar
+// registers, so each access is one global load or store with a scalar base and a
+// per-lane offset, with no 64-bit address arithmetic per access.  The base goes
+// through readfirstlane because otherwise the compiler folds the slot offset into
+// a shared per-lane address and rebuilds a 64-bit address for every access (about
+// 100 more VALU instructions per cell update); the integer round trip is cast back
+// to the global address space, or the accesses would become flat ones.  With the
+// 24-bit dither below, the FP16 kernels issue about 15% fewer VALU instructions
+// and the even-pair kernel needs 130 registers instead of 198.  FP32 keeps plain
+// pointer arithmetic: its byte offsets reach 2^33, and the step is bound by HBM
+// rather than by issue.
+__device__ __forceinline__ uint64_t wave_uniform(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <typename T>
+__device__ __forceinline__ T* at(T* base, int32_t cell) {
+  if constexpr (sizeof(T) == 2) {
+    typedef __attribute__((address_space(1))) char gchar;
+    gchar* b = (gchar*)wave_uniform(reinterpret_cast<uint64_t>(base));
+    return (T*)(b + ((uint32_t)cell << 1));
+  } else {
+    return base + cell;
+  }
+}
+template <typename T>
+__device__ __forceinline__ const T* at(const T* base, int32_t cell) {
+  return at(const_cast<T*>(base), cell);
+}
+
+// Address of f_i(x) for the read of an odd step (the location odd_src names).
+template <bool ZG, typename T>
+__device__ __forceinline__ const T* odd_at(const T* Fk, int64_t S, const Nbr& b, int i) {
+  switch (i) {
+    case 1: return (ZG && b.lo_x) ? at(Fk + 1 * S, b.n) : at(Fk + 2 * S, b.xm);
+    case 2: return (ZG && b.hi_x) ? at(Fk + 2 * S, b.n) : at(Fk + 1 * S, b.xp);
+    case 3: return (ZG && b.lo_y) ? at(Fk + 3 * S, b.n) : at(Fk + 4 * S, b.ym);
+    case 4: return (ZG && b.hi_y) ? at(Fk + 4 * S, b.n) : at(Fk + 3 * S, b.yp);
+    case 5: return (ZG && b.lo_z) ? at(Fk + 5 * S, b.n) : at(Fk + 6 * S, b.zm);
+    case 6: return (ZG && b.hi_z) ? at(Fk + 6 * S, b.n) : at(Fk + 5 * S, b.zp);
+    default: return at(Fk, b.n);
+  }
+}
+
 // ---------------------------------------------------------------- storage types
 template <typename T, bool NT>
 __device__ __forceinline__ float ld(const T* p) {
@@ -162,14 +210,27 @@ __host__ __device__ __forceinline__ uint32_t step_key(int64_t step) {
 // Hash of a destination cell under a step key.
 __device__ __forceinline__ uint32_t cell_key(int64_t cell, uint32_t skey) { return mix32((uint32_t)cell ^ skey); }
 
+// The 13 dither bits of slot `slot` of a cell keyed hc: bits 11..23 of the cell
+// key's low 24 bits times an odd 24-bit multiplier per slot.  Multiplication by an
+// odd number is a bijection modulo 2^24, so over all keys every 13-bit value occurs
+// equally often (exactly uniform).  The 24-bit multiply runs at full rate, where a
+// 32-bit one is a quarter-rate instruction; it is written as the instruction
+// because in C the compiler sees that the kept bits do not depend on the factors'
+// top 8 bits, drops the 24-bit masks and emits the 32-bit multiply.
+__device__ __forceinline__ uint32_t dither13(uint32_t hc, int slot) {
+  const uint32_t m = ((0x9e3779u + 2u * (uint32_t)slot * 0x6c8e9du) & 0xffffffu) | 1u;
+  uint32_t p;
+  asm("v_mul_u32_u24 %0, %1, %2" : "=v"(p) : "s"(m), "v"(hc));
+  return (p >> 11) & 0x1fffu;
+}
+
 // Stores population slot `slot` (7 k + i) of a cell whose key is hc.  FP32: plain
 // store.  FP16: stochastic rounding as above (the rounded value is exact in FP16,
 // so the conversion itself no longer rounds).
 template <typename T, bool NT>
 __device__ __forceinline__ void st_pop(T* p, float v, uint32_t hc, int slot) {
   if constexpr (sizeof(T) == 2) {
-    const uint32_t mul = 0x9e3779b9u + 2u * (uint32_t)slot * 0x6c8e9cf5u;  // odd per slot
-    const uint32_t dither = (hc * mul) >> 19;                               // 13 bits
+    const uint32_t dither = dither13(hc, slot);
     v = __uint_as_float((__float_as_uint(v) + dither) & 0xffffe000u);
   }
   st<T, NT>(p, v);
@@ -419,9 +480,9 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
       if constexpr (ODD) {
-        f[7 * k + i] = ld<T, NT>(Fk + odd_src<ZG>(g, b, i));
+        f[7 * k + i] = ld<T, NT>(odd_at<ZG>(Fk, S, b, i));
       } else {
-        f[7 * k + i] = ld<T, NT>(Fk + (int64_t)i * S + b.n);
+        f[7 * k + i] = ld<T, NT>(at(Fk + (int64_t)i * S, b.n));
       }
     }
   }
@@ -456,30 +517,30 @@ __device__ __forceinline__ void cell_update(T* __restrict__ F, const Grid& g, co
     if constexpr (!ODD) {
       // own cell, opposite slot; on a zero-gradient face the ghost copy replaces
       // the population that leaves the domain
-      st_pop<T, NT>(Fk + b.n, fo[0], hn, s0);
-      st_pop<T, NT>(Fk + 1 * S + b.n, (ZG && b.lo_x) ? fo[1] : fo[2], hn, s0 + 1);
-      st_pop<T, NT>(Fk + 2 * S + b.n, (ZG && b.hi_x) ? fo[2] : fo[1], hn, s0 + 2);
-      st_pop<T, NT>(Fk + 3 * S + b.n, (ZG && b.lo_y) ? fo[3] : fo[4], hn, s0 + 3);
-      st_pop<T, NT>(Fk + 4 * S + b.n, (ZG && b.hi_y) ? fo[4] : fo[3], hn, s0 + 4);
-      st_pop<T, NT>(Fk + 5 * S + b.n, (ZG && b.lo_z) ? fo[5] : fo[6], hn, s0 + 5);
-      st_pop<T, NT>(Fk + 6 * S + b.n, (ZG && b.hi_z) ? fo[6] : fo[5], hn, s0 + 6);
+      st_pop<T, NT>(at(Fk, b.n), fo[0], hn, s0);
+      st_pop<T, NT>(at(Fk + 1 * S, b.n), (ZG && b.lo_x) ? fo[1] : fo[2], hn, s0 + 1);
+      st_pop<T, NT>(at(Fk + 2 * S, b.n), (ZG && b.hi_x) ? fo[2] : fo[1], hn, s0 + 2);
+      st_pop<T, NT>(at(Fk + 3 * S, b.n), (ZG && b.lo_y) ? fo[3] : fo[4], hn, s0 + 3);
+      st_pop<T, NT>(at(Fk + 4 * S, b.n), (ZG && b.hi_y) ? fo[4] : fo[3], hn, s0 + 4);
+      st_pop<T, NT>(at(Fk + 5 * S, b.n), (ZG && b.lo_z) ? fo[5] : fo[6], hn, s0 + 5);
+      st_pop<T, NT>(at(Fk + 6 * S, b.n), (ZG && b.hi_z) ? fo[6] : fo[5], hn, s0 + 6);
     } else {
       // slot i of the downstream cell x + c_i
-      st_pop<T, NT>(Fk + b.n, fo[0], hn, s0);
-      if (!(ZG && b.hi_x)) st_pop<T, NT>(Fk + 1 * S + b.xp, fo[1], hxp, s0 + 1);
-      if (!(ZG && b.lo_x)) st_pop<T, NT>(Fk + 2 * S + b.xm, fo[2], hxm, s0 + 2);
-      if (!(ZG && b.hi_y)) st_pop<T, NT>(Fk + 3 * S + b.yp, fo[3], hyp, s0 + 3);
-      if (!(ZG && b.lo_y)) st_pop<T, NT>(Fk + 4 * S + b.ym, fo[4], hym, s0 + 4);
-      if (!(ZG && b.hi_z)) st_pop<T, NT>(Fk + 5 * S + b.zp, fo[5], hzp, s0 + 5);
-      if (!(ZG && b.lo_z)) st_pop<T, NT>(Fk + 6 * S + b.zm, fo[6], hzm, s0 + 6);
+      st_pop<T, NT>(at(Fk, b.n), fo[0], hn, s0);
+      if (!(ZG && b.hi_x)) st_pop<T, NT>(at(Fk + 1 * S, b.xp), fo[1], hxp, s0 + 1);
+      if (!(ZG && b.lo_x)) st_pop<T, NT>(at(Fk + 2 * S, b.xm), fo[2], hxm, s0 + 2);
+      if (!(ZG && b.hi_y)) st_pop<T, NT>(at(Fk + 3 * S, b.yp), fo[3], hyp, s0 + 3);
+      if (!(ZG && b.lo_y)) st_pop<T, NT>(at(Fk + 4 * S, b.ym), fo[4], hym, s0 + 4);
+      if (!(ZG && b.hi_z)) st_pop<T, NT>(at(Fk + 5 * S, b.zp), fo[5], hzp, s0 + 5);
+      if (!(ZG && b.lo_z)) st_pop<T, NT>(at(Fk + 6 * S, b.zm), fo[6], hzm, s0 + 6);
       if constexpr (ZG) {
         // ghost copy entering through a zero-gradient face
-        if (b.lo_x) st_pop<T, NT>(Fk + 1 * S + b.n, fo[1], hn, s0 + 1);
-        if (b.hi_x) st_pop<T, NT>(Fk + 2 * S + b.n, fo[2], hn, s0 + 2);
-        if (b.lo_y) st_pop<T, NT>(Fk + 3 * S + b.n, fo[3], hn, s0 + 3);
-        if (b.hi_y) st_pop<T, NT>(Fk + 4 * S + b.n, fo[4], hn, s0 + 4);
-        if (b.lo_z) st_pop<T, NT>(Fk + 5 * S + b.n, fo[5], hn, s0 + 5);
-        if (b.hi_z) st_pop<T, NT>(Fk + 6 * S + b.n, fo[6], hn, s0 + 6);
+        if (b.lo_x) st_pop<T, NT>(at(Fk + 1 * S, b.n), fo[1], hn, s0 + 1);
+        if (b.hi_x) st_pop<T, NT>(at(Fk + 2 * S, b.n), fo[2], hn, s0 + 2);
+        if (b.lo_y) st_pop<T, NT>(at(Fk + 3 * S, b.n), fo[3], hn, s0 + 3);
+        if (b.hi_y) st_pop<T, NT>(at(Fk + 4 * S, b.n), fo[4], hn, s0 + 4);
+        if (b.lo_z) st_pop<T, NT>(at(Fk + 5 * S, b.n), fo[5], hn, s0 + 5);
+        if (b.hi_z) st_pop<T, NT>(at(Fk + 6 * S, b.n), fo[6], hn, s0 + 6);
       }
     }
   }
@@ -516,8 +577,7 @@ __device__ __forceinline__ float half_hi(uint32_t w) {
 }
 // The FP16 bits st_pop<_Float16> stores for v.
 __device__ __forceinline__ uint32_t half_bits(float v, uint32_t hc, int slot) {
-  const uint32_t mul = 0x9e3779b9u + 2u * (uint32_t)slot * 0x6c8e9cf5u;
-  const uint32_t dither = (hc * mul) >> 19;
+  const uint32_t dither = dither13(hc, slot);
   v = __uint_as_float((__float_as_uint(v) + dither) & 0xffffe000u);
   asm volatile("" : "+v"(v));
   return (uint32_t)__builtin_bit_cast(uint16_t, static_cast<_Float16>(v));
@@ -529,7 +589,7 @@ __device__ __forceinline__ void pair_update_even(_Float16* __restrict__ F, const
   const int64_t S = g.S;
   uint32_t w[kPop];  // slot pairs: inputs, overwritten half by half with the outputs
 #pragma unroll
-  for (int s = 0; s < kPop; ++s) w[s] = ld_pair<NT>(F + (int64_t)s * S + n);
+  for (int s = 0; s < kPop; ++s) w[s] = ld_pair<NT>(at(F + (int64_t)s * S, n));
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     // one cell at a time: the second cell's inputs stay packed until its turn
@@ -584,7 +644,7 @@ __device__ __forceinline__ void pair_update_even(_Float16* __restrict__ F, const
     }
   }
 #pragma unroll
-  for (int s = 0; s < kPop; ++s) st_pair<NT>(F + (int64_t)s * S + n, w[s]);
+  for (int s = 0; s < kPop; ++s) st_pair<NT>(at(F + (int64_t)s * S, n), w[s]);
 }
 
 // ----------------------------------------------------- odd update of one tile
@@ -628,11 +688,11 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
 #pragma unroll
     for (int k = 0; k < kFields; ++k) {
       const T* Fk = F + (int64_t)(7 * k) * S;
-      s1[k * B + lane] = ld<T, NT>(Fk + 1 * S + b.n);
-      s2[k * B + lane] = ld<T, NT>(Fk + 2 * S + b.n);
-      f[7 * k + 0] = ld<T, NT>(Fk + b.n);
+      s1[k * B + lane] = ld<T, NT>(at(Fk + 1 * S, b.n));
+      s2[k * B + lane] = ld<T, NT>(at(Fk + 2 * S, b.n));
+      f[7 * k + 0] = ld<T, NT>(at(Fk, b.n));
 #pragma unroll
-      for (int i = 3; i < kQ; ++i) f[7 * k + i] = ld<T, NT>(Fk + odd_src<ZG>(g, b, i));
+      for (int i = 3; i < kQ; ++i) f[7 * k + i] = ld<T, NT>(odd_at<ZG>(Fk, S, b, i));
     }
   }
   const bool lo = ZG && b.lo_x;
@@ -647,11 +707,11 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
   float d1[kFields], d2[kFields];
   if (act && !in1) {
 #pragma unroll
-    for (int k = 0; k < kFields; ++k) d1[k] = ld<T, NT>(F + (int64_t)(7 * k + 2) * S + m1);
+    for (int k = 0; k < kFields; ++k) d1[k] = ld<T, NT>(at(F + (int64_t)(7 * k + 2) * S, m1));
   }
   if (act && !in2) {
 #pragma unroll
-    for (int k = 0; k < kFields; ++k) d2[k] = ld<T, NT>(F + (int64_t)(7 * k + 1) * S + m2);
+    for (int k = 0; k < kFields; ++k) d2[k] = ld<T, NT>(at(F + (int64_t)(7 * k + 1) * S, m2));
   }
   __syncthreads();
   const float* r1 = (lo ? s1 : s2) + (in1 ? m1 - n0 : lane);
@@ -696,16 +756,16 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
       T* Fk = F + (int64_t)(7 * k) * S;
       const float* fo = f + 7 * k;
       const int s0 = 7 * k;
-      st_pop<T, NT>(Fk + b.n, fo[0], hn, s0);
-      if (!(ZG && b.hi_y)) st_pop<T, NT>(Fk + 3 * S + b.yp, fo[3], hyp, s0 + 3);
-      if (!(ZG && b.lo_y)) st_pop<T, NT>(Fk + 4 * S + b.ym, fo[4], hym, s0 + 4);
-      if (!(ZG && b.hi_z)) st_pop<T, NT>(Fk + 5 * S + b.zp, fo[5], hzp, s0 + 5);
-      if (!(ZG && b.lo_z)) st_pop<T, NT>(Fk + 6 * S + b.zm, fo[6], hzm, s0 + 6);
+      st_pop<T, NT>(at(Fk, b.n), fo[0], hn, s0);
+      if (!(ZG && b.hi_y)) st_pop<T, NT>(at(Fk + 3 * S, b.yp), fo[3], hyp, s0 + 3);
+      if (!(ZG && b.lo_y)) st_pop<T, NT>(at(Fk + 4 * S, b.ym), fo[4], hym, s0 + 4);
+      if (!(ZG && b.hi_z)) st_pop<T, NT>(at(Fk + 5 * S, b.zp), fo[5], hzp, s0 + 5);
+      if (!(ZG && b.lo_z)) st_pop<T, NT>(at(Fk + 6 * S, b.zm), fo[6], hzm, s0 + 6);
       if constexpr (ZG) {
-        if (b.lo_y) st_pop<T, NT>(Fk + 3 * S + b.n, fo[3], hn, s0 + 3);
-        if (b.hi_y) st_pop<T, NT>(Fk + 4 * S + b.n, fo[4], hn, s0 + 4);
-        if (b.lo_z) st_pop<T, NT>(Fk + 5 * S + b.n, fo[5], hn, s0 + 5);
-        if (b.hi_z) st_pop<T, NT>(Fk + 6 * S + b.n, fo[6], hn, s0 + 6);
+        if (b.lo_y) st_pop<T, NT>(at(Fk + 3 * S, b.n), fo[3], hn, s0 + 3);
+        if (b.hi_y) st_pop<T, NT>(at(Fk + 4 * S, b.n), fo[4], hn, s0 + 4);
+        if (b.lo_z) st_pop<T, NT>(at(Fk + 5 * S, b.n), fo[5], hn, s0 + 5);
+        if (b.hi_z) st_pop<T, NT>(at(Fk + 6 * S, b.n), fo[6], hn, s0 + 6);
       }
       w1[k * B] = fo[1];
       w2[k * B] = fo[2];
@@ -717,12 +777,12 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
     if (!hi && !in2) {
       const uint32_t h = sizeof(T) == 2 ? cell_key(b.xp, skey) : 0u;
 #pragma unroll
-      for (int k = 0; k < kFields; ++k) st_pop<T, NT>(F + (int64_t)(7 * k + 1) * S + b.xp, f[7 * k + 1], h, 7 * k + 1);
+      for (int k = 0; k < kFields; ++k) st_pop<T, NT>(at(F + (int64_t)(7 * k + 1) * S, b.xp), f[7 * k + 1], h, 7 * k + 1);
     }
     if (!lo && !in1) {
       const uint32_t h = sizeof(T) == 2 ? cell_key(b.xm, skey) : 0u;
 #pragma unroll
-      for (int k = 0; k < kFields; ++k) st_pop<T, NT>(F + (int64_t)(7 * k + 2) * S + b.xm, f[7 * k + 2], h, 7 * k + 2);
+      for (int k = 0; k < kFields; ++k) st_pop<T, NT>(at(F + (int64_t)(7 * k + 2) * S, b.xm), f[7 * k + 2], h, 7 * k + 2);
     }
   }
   __syncthreads();
@@ -730,11 +790,11 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
   const uint32_t hown = (sizeof(T) == 2 && act) ? cell_key(b.n, skey) : 0u;
   if (act && in1) {
 #pragma unroll
-    for (int k = 0; k < kFields; ++k) st_pop<T, NT>(F + (int64_t)(7 * k + 1) * S + b.n, s1[k * B + lane], hown, 7 * k + 1);
+    for (int k = 0; k < kFields; ++k) st_pop<T, NT>(at(F + (int64_t)(7 * k + 1) * S, b.n), s1[k * B + lane], hown, 7 * k + 1);
   }
   if (act && in2) {
 #pragma unroll
-    for (int k = 0; k < kFields; ++k) st_pop<T, NT>(F + (int64_t)(7 * k + 2) * S + b.n, s2[k * B + lane], hown, 7 * k + 2);
+    for (int k = 0; k < kFields; ++k) st_pop<T, NT>(at(F + (int64_t)(7 * k + 2) * S, b.n), s2[k * B + lane], hown, 7 * k + 2);
   }
 }
 
@@ -769,15 +829,15 @@ __device__ __forceinline__ void pair_row_update_odd(_Float16* __restrict__ F, co
 #pragma unroll
   for (int k = 0; k < kFields; ++k) {
     const _Float16* Fk = F + (int64_t)(7 * k) * S;
-    const uint32_t p1 = ld_pair<NT>(Fk + 1 * S + b.n);
-    const uint32_t p2 = ld_pair<NT>(Fk + 2 * S + b.n);
+    const uint32_t p1 = ld_pair<NT>(at(Fk + 1 * S, b.n));
+    const uint32_t p2 = ld_pair<NT>(at(Fk + 2 * S, b.n));
     s1[k * nx + x0] = half_lo(p1);
     s1[k * nx + x0 + 1] = half_hi(p1);
     s2[k * nx + x0] = half_lo(p2);
     s2[k * nx + x0 + 1] = half_hi(p2);
-    w[7 * k] = ld_pair<NT>(Fk + b.n);
+    w[7 * k] = ld_pair<NT>(at(Fk, b.n));
 #pragma unroll
-    for (int i = 3; i < kQ; ++i) w[7 * k + i] = ld_pair<NT>(Fk + odd_src<ZG>(g, b, i));
+    for (int i = 3; i < kQ; ++i) w[7 * k + i] = ld_pair<NT>(odd_at<ZG>(Fk, S, b, i));
   }
   __syncthreads();
   // where the two stores of each axis go: (slot, cell) of the first and the second
@@ -852,7 +912,7 @@ __device__ __forceinline__ void pair_row_update_odd(_Float16* __restrict__ F, co
 #pragma unroll
   for (int k = 0; k < kFields; ++k) {
     _Float16* Fk = F + (int64_t)(7 * k) * S;
-    st_pair<NT>(Fk + b.n, w[7 * k]);
+    st_pair<NT>(at(Fk, b.n), w[7 * k]);
 #pragma unroll
     for (int j = 0; j < 4; ++j) st_pair<NT>(Fk + dst[j], w[7 * k + 3 + j]);
   }
@@ -862,9 +922,9 @@ __device__ __forceinline__ void pair_row_update_odd(_Float16* __restrict__ F, co
 #pragma unroll
   for (int k = 0; k < kFields; ++k) {
     _Float16* Fk = F + (int64_t)(7 * k) * S;
-    st_pair<NT>(Fk + 1 * S + b.n, half_bits(s1[k * nx + x0], ha, 7 * k + 1) |
+    st_pair<NT>(at(Fk + 1 * S, b.n), half_bits(s1[k * nx + x0], ha, 7 * k + 1) |
                                       (half_bits(s1[k * nx + x0 + 1], hb, 7 * k + 1) << 16));
-    st_pair<NT>(Fk + 2 * S + b.n, half_bits(s2[k * nx + x0], ha, 7 * k + 2) |
+    st_pair<NT>(at(Fk + 2 * S, b.n), half_bits(s2[k * nx + x0], ha, 7 * k + 2) |
                                       (half_bits(s2[k * nx + x0 + 1], hb, 7 * k + 2) << 16));
   }
 }
