@@ -840,10 +840,7 @@ __device__ __forceinline__ void pair_row_update_odd(_Float16* __restrict__ F, co
     for (int i = 3; i < kQ; ++i) w[7 * k + i] = ld_pair<NT>(odd_at<ZG>(Fk, S, b, i));
   }
   __syncthreads();
-  // where the two stores of each axis go: (slot, cell) of the first and the second
   const bool ylo = ZG && b.lo_y, yhi = ZG && b.hi_y, zlo = ZG && b.lo_z, zhi = ZG && b.hi_z;
-  const int64_t dst[4] = {yhi ? 4 * S + b.n : 3 * S + b.yp, ylo ? 3 * S + b.n : 4 * S + b.ym,
-                          zhi ? 6 * S + b.n : 5 * S + b.zp, zlo ? 5 * S + b.n : 6 * S + b.zm};
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     if (h == 1) {
@@ -912,9 +909,14 @@ __device__ __forceinline__ void pair_row_update_odd(_Float16* __restrict__ F, co
 #pragma unroll
   for (int k = 0; k < kFields; ++k) {
     _Float16* Fk = F + (int64_t)(7 * k) * S;
+    // where the two stores of each axis go: (slot, cell) of the first and the second
+    _Float16* const dst[4] = {yhi ? at(Fk + 4 * S, b.n) : at(Fk + 3 * S, b.yp),
+                              ylo ? at(Fk + 3 * S, b.n) : at(Fk + 4 * S, b.ym),
+                              zhi ? at(Fk + 6 * S, b.n) : at(Fk + 5 * S, b.zp),
+                              zlo ? at(Fk + 5 * S, b.n) : at(Fk + 6 * S, b.zm)};
     st_pair<NT>(at(Fk, b.n), w[7 * k]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) st_pair<NT>(Fk + dst[j], w[7 * k + 3 + j]);
+    for (int j = 0; j < 4; ++j) st_pair<NT>(dst[j], w[7 * k + 3 + j]);
   }
   __syncthreads();
   // write back both cells' x slots, rounded with their own keys
