@@ -204,9 +204,15 @@ __global__ void __launch_bounds__(1024) k_finalize(const float* __restrict__ par
 }
 
 // Largest |v| per field, as the bit pattern of a non-negative float (which orders
-// like the value); the result does not depend on the order of the atomics.
-__device__ __forceinline__ void field_max(unsigned* maxabs, int k, float v) {
-  atomicMax(maxabs + k, __float_as_uint(fabsf(v)));
+// like the value); the result does not depend on the order of the atomics.  The
+// wave reduces first and issues one atomic per field: one atomic per cell on the
+// same five words serialised and took 15 ms at 256^3.  Every lane of the wave must
+// call it; lanes without a cell pass 0.  A NaN does not win the maximum.
+__device__ __forceinline__ void wave_field_max(unsigned* maxabs, int k, float v) {
+  float m = fabsf(v);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(maxabs + k, __float_as_uint(m));
 }
 
 // Neighbour index along one axis for a central difference: periodic wrap, or the
@@ -230,14 +236,11 @@ __device__ __forceinline__ int64_t fd_neighbour(int64_t n, int x, int d, int len
 // omega -> 2.  Computed in FP64, stored as g_i = w_i (Q - Q_ref + 4 c_i . J) times
 // the field's storage scale.  With ic.equilibrium (initial data with jumps, where a
 // difference across a jump is no gradient) grad Q is taken as zero, which leaves
-// the equilibrium of Q with the advective flux.  With maxabs set, nothing is stored
-// and the largest |g| of each field is reduced instead (used to pick the FP16 scales).
+// the equilibrium of Q with the advective flux.  With mx set, nothing is stored and
+// mx[k] receives the cell's largest |g| of field k (used to pick the FP16 scales).
 template <typename T>
-__global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c, InitCoef ic,
-                                               const double* __restrict__ Q, int64_t N,
-                                               unsigned* __restrict__ maxabs) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+__device__ __forceinline__ void init_cell(T* __restrict__ F, const Grid& g, const Coll& c, const InitCoef& ic,
+                                          const double* __restrict__ Q, int64_t N, int64_t n, float* mx) {
   const int64_t row = n / g.nx;
   const int x = (int)(n - row * g.nx);
   const int y = (int)(row % g.ny);
@@ -298,10 +301,10 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
     const float v[7] = {(float)(0.25 * dq),           (float)(q8 + 0.5 * J[k][0]), (float)(q8 - 0.5 * J[k][0]),
                         (float)(q8 + 0.5 * J[k][1]), (float)(q8 - 0.5 * J[k][1]), (float)(q8 + 0.5 * J[k][2]),
                         (float)(q8 - 0.5 * J[k][2])};
-    if (maxabs) {
+    if (mx) {
       float m = 0.0f;
       for (int i = 0; i < kQ; ++i) m = fmaxf(m, fabsf(v[i]));
-      field_max(maxabs, k, m);
+      mx[k] = m;
     } else {
       T* Fk = F + (int64_t)(7 * k) * g.S + ns;
       for (int i = 0; i < kQ; ++i) Fk[(int64_t)i * g.S] = static_cast<T>(v[i] * c.sc[k]);
@@ -310,15 +313,41 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c,
 }
 
 // Largest |f| per field of a canonical population array f[35][N].
+template <typename T>
+__global__ void __launch_bounds__(256) k_init(T* __restrict__ F, Grid g, Coll c, InitCoef ic,
+                                               const double* __restrict__ Q, int64_t N) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < N) init_cell<T>(F, g, c, ic, Q, N, n, nullptr);
+}
+
+// The largest |g| of each field over the initial populations k_init would store,
+// without storing them (picks the FP16 scales).  A fixed grid of at most 2048
+// blocks strides over the cells, so the atomics number a few per wave and not
+// one per wave of cells.
+__global__ void __launch_bounds__(256) k_init_maxabs(Grid g, Coll c, InitCoef ic, const double* __restrict__ Q,
+                                                      int64_t N, unsigned* __restrict__ maxabs) {
+  float mx[kFields] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+    float m[kFields];
+    init_cell<float>(nullptr, g, c, ic, Q, N, n, m);
+#pragma unroll
+    for (int k = 0; k < kFields; ++k) mx[k] = fmaxf(mx[k], m[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kFields; ++k) wave_field_max(maxabs, k, mx[k]);
+}
+
+// The same over populations handed in by the caller (canonical layout, N cells).
 __global__ void __launch_bounds__(256) k_maxabs_pops(const float* __restrict__ f, int64_t N,
                                                       unsigned* __restrict__ maxabs) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  for (int k = 0; k < 5; ++k) {
-    float m = 0.0f;
-    for (int i = 0; i < kQ; ++i) m = fmaxf(m, fabsf(f[(int64_t)(7 * k + i) * N + n]));
-    field_max(maxabs, k, m);
+  float mx[kFields] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kFields; ++k)
+      for (int i = 0; i < kQ; ++i) mx[k] = fmaxf(mx[k], fabsf(f[(int64_t)(7 * k + i) * N + n]));
   }
+#pragma unroll
+  for (int k = 0; k < kFields; ++k) wave_field_max(maxabs, k, mx[k]);
 }
 
 // Element offset of canonical f_i of field k at the lane's cell for a state of
@@ -524,22 +553,26 @@ hipError_t launch_init(void* F, bool f16, const Grid& g, const Coll& c, const In
                        int64_t N, hipStream_t s) {
   const unsigned blocks = (unsigned)((N + 255) / 256);
   if (f16)
-    hipLaunchKernelGGL(k_init<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, c, ic, Q, N, nullptr);
+    hipLaunchKernelGGL(k_init<_Float16>, dim3(blocks), dim3(256), 0, s, (_Float16*)F, g, c, ic, Q, N);
   else
-    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, c, ic, Q, N, nullptr);
+    hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, (float*)F, g, c, ic, Q, N);
   return hipGetLastError();
+}
+
+// Blocks of the striding max-abs reductions: 8 per CU, a few thousand atomics.
+static unsigned maxabs_blocks(int64_t N) {
+  const int64_t b = (N + 255) / 256;
+  return (unsigned)(b < 2048 ? (b > 0 ? b : 1) : 2048);
 }
 
 hipError_t launch_init_maxabs(const Grid& g, const Coll& c, const InitCoef& ic, const double* Q, int64_t N,
                               unsigned* maxabs, hipStream_t s) {
-  const unsigned blocks = (unsigned)((N + 255) / 256);
-  hipLaunchKernelGGL(k_init<float>, dim3(blocks), dim3(256), 0, s, nullptr, g, c, ic, Q, N, maxabs);
+  hipLaunchKernelGGL(k_init_maxabs, dim3(maxabs_blocks(N)), dim3(256), 0, s, g, c, ic, Q, N, maxabs);
   return hipGetLastError();
 }
 
 hipError_t launch_maxabs_pops(const float* f, int64_t N, unsigned* maxabs, hipStream_t s) {
-  const unsigned blocks = (unsigned)((N + 255) / 256);
-  hipLaunchKernelGGL(k_maxabs_pops, dim3(blocks), dim3(256), 0, s, f, N, maxabs);
+  hipLaunchKernelGGL(k_maxabs_pops, dim3(maxabs_blocks(N)), dim3(256), 0, s, f, N, maxabs);
   return hipGetLastError();
 }
 
