@@ -143,9 +143,15 @@ class Server:
         # "fifo": admit arrived requests in arrival order, the first that does not
         # fit blocks the rest; "largest": among the arrived requests, largest work
         # (cells x steps) first, skipping those that do not fit yet, except that
-        # requests waiting longer than max_wait_s go first in arrival order and keep
-        # their place while they do not fit (so neither a stream of large requests
-        # nor one of small ones can hold a request back without bound)
+        # requests waiting longer than max_wait_s go first in arrival order.  The
+        # first overdue request that does not fit holds a reservation: all
+        # instances advance one step per step, so the chunk at which enough of
+        # the running ones have finished for it to fit (its shadow) is known
+        # exactly, and a later request is admitted meanwhile only if it finishes
+        # by then or fits beside it in what is left at that chunk (backfilling).
+        # So neither a stream of large requests nor one of small ones can hold a
+        # request back without bound, and the device is not left half empty
+        # while the overdue request waits.
         if order not in ("fifo", "largest"):
             raise ValueError(f"order must be 'fifo' or 'largest', not {order!r}")
         self.order = order
@@ -164,6 +170,46 @@ class Server:
             return 0
         return r.storage
 
+    def _chunks(self, steps: int) -> int:
+        """Chunks until an instance with `steps` steps left retires."""
+        return -(-max(int(steps), 0) // self.chunk)
+
+    def _reserve(self, r, nb, active, used_bytes, used_cells, steps_run, fragmented=False):
+        """Reservation for request r that does not fit now: the chunk at which it
+        will (running instances retire in order of their remaining steps) and the
+        bytes, cells and instance slots left beside it then."""
+        rem = sorted((self._chunks(q.steps - (steps_run - s0)), b, q.case.cells) for q, b, s0 in active.values())
+        fb = fc = fn = 0
+        at = rem[0][0] if rem else 0
+        for ch, b, c in rem:  # at least one retirement: r does not fit (or find room) now
+            fb, fc, fn = fb + b, fc + c, fn + 1
+            at = ch
+            left = len(active) - fn
+            if (used_bytes - fb + nb <= self.arena_bytes and left < self.max_instances and
+                    (self.max_cells is None or left == 0 or used_cells - fc + r.case.cells <= self.max_cells)):
+                break
+        extra_b = self.arena_bytes - (used_bytes - fb) - nb
+        extra_c = None if self.max_cells is None else self.max_cells - (used_cells - fc) - r.case.cells
+        extra_n = self.max_instances - (len(active) - fn) - 1
+        if fragmented:  # the byte count fits but no free run does: no room beside it
+            extra_b = extra_n = 0
+            extra_c = None if self.max_cells is None else 0
+        return {"at": at, "bytes": extra_b, "cells": extra_c, "n": extra_n}
+
+    def _backfills(self, hold, r, nb) -> bool:
+        """Whether request r may start now without delaying the held request: it
+        finishes by the held request's chunk, or fits in what is left beside it
+        (which it then takes)."""
+        if self._chunks(r.steps) <= hold["at"]:
+            return True
+        if nb <= hold["bytes"] and hold["n"] >= 1 and (hold["cells"] is None or r.case.cells <= hold["cells"]):
+            hold["bytes"] -= nb
+            hold["n"] -= 1
+            if hold["cells"] is not None:
+                hold["cells"] -= r.case.cells
+            return True
+        return False
+
     @staticmethod
     def _reject(o: Outcome, now: float, why: str) -> None:
         o.ok = False
@@ -174,29 +220,43 @@ class Server:
         reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
         stg = {r.rid: self.storage_of(r) for r in reqs}
         out = {r.rid: Outcome(r.rid, r.kind, stg[r.rid], r.case.cells, r.steps, r.arrival) for r in reqs}
-        pending = list(reqs)
-        active = {}                 # instance id -> (request, bytes)
+        nbytes = {r.rid: state_bytes(r.case.params, stg[r.rid]) for r in reqs}
+        ncells = {r.rid: r.case.cells for r in reqs}
+        work = {r.rid: ncells[r.rid] * r.steps for r in reqs}
+        # request id -> request, in arrival order (ids, not request equality, on the
+        # hot path: comparing requests compares their arrays)
+        pending = {r.rid: r for r in reqs}
+        active = {}                 # instance id -> (request, bytes, steps run when admitted)
         used_bytes = 0
         used_cells = 0
+        steps_run = 0               # steps every resident instance has been offered so far
         st = ServeStats()
         t0 = self.clock()
         while pending or active:
             now = self.clock() - t0
             # admission: arrived requests while memory and the cell cap allow
-            arrived = [r for r in pending if r.arrival <= now]
-            overdue = []
+            arrived = []
+            for r in pending.values():
+                if r.arrival > now:
+                    break
+                arrived.append(r)
+            overdue = set()
             if self.order == "largest":
-                overdue = [r for r in arrived if self.max_wait is not None and now - r.arrival > self.max_wait]
-                rest = sorted((r for r in arrived if r not in overdue), key=lambda r: -r.case.cells * r.steps)
-                arrived = overdue + rest
+                late = [r for r in arrived if self.max_wait is not None and now - r.arrival > self.max_wait]
+                overdue = {r.rid for r in late}
+                rest = sorted((r for r in arrived if r.rid not in overdue), key=lambda r: -work[r.rid])
+                arrived = late + rest
+            hold = None  # reservation of the first overdue request that does not fit
             for r in arrived:
-                nb = state_bytes(r.case.params, stg[r.rid])
+                nb = nbytes[r.rid]
                 if nb > self.arena_bytes:
                     self._reject(out[r.rid], now, "larger than the HBM budget")
-                    pending.remove(r)
+                    del pending[r.rid]
                     continue
                 fits = used_bytes + nb <= self.arena_bytes and len(active) < self.max_instances and not (
-                    self.max_cells is not None and active and used_cells + r.case.cells > self.max_cells)
+                    self.max_cells is not None and active and used_cells + ncells[r.rid] > self.max_cells)
+                if fits and hold is not None and not self._backfills(hold, r, nb):
+                    continue
                 if fits:
                     try:
                         iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=stg[r.rid])
@@ -206,29 +266,32 @@ class Server:
                             # the library refuses the request itself (e.g. an initial
                             # state with non-positive density or pressure)
                             self._reject(out[r.rid], self.clock() - t0, str(e))
-                            pending.remove(r)
+                            del pending[r.rid]
                             continue
                         # no free run of that size yet (fragmentation): wait for retirements
                         if status != ENOMEM or not active:
                             raise
                         fits = False
+                        if hold is None and r.rid in overdue:
+                            hold = self._reserve(r, nb, active, used_bytes, used_cells, steps_run,
+                                                 fragmented=True)
+                        continue
                 if not fits:
-                    if self.order == "fifo" or r in overdue:
-                        # an overdue request keeps its place: nothing behind it is
-                        # admitted until it fits, so later arrivals cannot take the
-                        # memory it waits for
+                    if self.order == "fifo":
                         break
+                    if hold is None and r.rid in overdue:
+                        hold = self._reserve(r, nb, active, used_bytes, used_cells, steps_run)
                     continue
-                pending.remove(r)
-                active[iid] = (r, nb)
+                del pending[r.rid]
+                active[iid] = (r, nb, steps_run)
                 used_bytes += nb
-                used_cells += r.case.cells
+                used_cells += ncells[r.rid]
                 out[r.rid].admitted = self.clock() - t0
             st.max_active = max(st.max_active, len(active))
             st.peak_bytes = max(st.peak_bytes, used_bytes)
             if not active:
                 # idle until the next arrival
-                wait = pending[0].arrival - (self.clock() - t0)
+                wait = next(iter(pending.values())).arrival - (self.clock() - t0)
                 if wait > 0:
                     time.sleep(min(wait, 0.05))
                 continue
@@ -236,12 +299,13 @@ class Server:
             # reaches its step count inside the chunk stays frozen there
             t_start = self.clock() - t0
             self.b.run(self.chunk)
+            steps_run += self.chunk
             st.chunks += 1
             self.sync()
             tnow = self.clock() - t0
             st.timeline.append((t_start, tnow, len(active), used_cells))
             for iid in [i for i in active if self.b.query(i)[1]]:
-                r, nb = active.pop(iid)
+                r, nb, _ = active.pop(iid)
                 Q = self.b.moments(iid)
                 o = out[r.rid]
                 o.completed = tnow
@@ -250,18 +314,18 @@ class Server:
                 o.result = res
                 self.b.remove(iid)
                 used_bytes -= nb
-                used_cells -= r.case.cells
+                used_cells -= ncells[r.rid]
             if self.check is not None and active and st.chunks % self.check_chunks == 0:
                 for iid in self.check():
                     if iid not in active:
                         continue
-                    r, nb = active.pop(iid)
+                    r, nb, _ = active.pop(iid)
                     o = out[r.rid]
                     o.completed = tnow
                     o.ok = False
                     self.b.remove(iid)
                     used_bytes -= nb
-                    used_cells -= r.case.cells
+                    used_cells -= ncells[r.rid]
                     st.stopped += 1
                     if self.on_failure is not None:
                         self.on_failure(r)

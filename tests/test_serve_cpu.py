@@ -179,6 +179,28 @@ def test_overdue_request_keeps_its_place():
     assert starved.admitted > 0.08 > waited.admitted     # without the bound it waits for every small one
 
 
+def test_overdue_reservation_backfills_short_requests():
+    """While an overdue request waits for room, requests that finish before the
+    room is there (its shadow) run meanwhile, and one that would still hold memory
+    then waits: the overdue request starts exactly when the instance ahead of it
+    retires, as it would with nothing admitted behind it."""
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    M = make_req(0, 0.0, 1600, 100)                                          # running, 10 chunks
+    B = make_req(1, 0.001, 3200, 20)                                         # does not fit beside M
+    S = [make_req(2 + i, 0.02 + 0.01 * i, 320, 10) for i in range(3)]       # one chunk each
+    L = make_req(9, 0.02, 640, 500)                                          # long, and too big to sit beside B
+    budget = serve.state_bytes(B.case.params, 0) + serve.state_bytes(S[0].case.params, 0)
+    st = serve.Server(fb, arena_bytes=budget, chunk_steps=10, clock=clk, order="largest",
+                      max_wait_s=0.005).serve([M, B, *S, L])
+    o = {x.rid: x for x in st.outcomes}
+    assert all(x.ok for x in o.values())
+    assert o[1].admitted == pytest.approx(o[0].completed)
+    for x in S:
+        assert o[x.rid].admitted < o[1].admitted and o[x.rid].completed <= o[1].admitted
+    assert o[9].admitted >= o[1].admitted
+
+
 def test_unknown_order_rejected():
     with pytest.raises(ValueError):
         serve.Server(FakeBatch(FakeClock()), arena_bytes=1, order="random")
