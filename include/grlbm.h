@@ -291,8 +291,8 @@ typedef struct {
  * instances, room for max_instances descriptors and max_tiles tiles per group, and
  * time loops captured in graphs of graph_steps steps (1..4096; 1 = no graph).
  * hip_stream as for lbm_create.  The launch shape starts as one 256-cell tile per
- * block with plain (not nontemporal) access (block 256, nontemporal 0,
- * blocks_per_cu 0, grid 0).  EINVAL on bad sizes, ENOMEM if the arena does not
+ * block with plain (not nontemporal) access and at most 2 blocks per CU (block
+ * 256, nontemporal 0, blocks_per_cu 2, grid 0).  EINVAL on bad sizes, ENOMEM if the arena does not
  * fit. */
 lbm_status lbm_batch_create(size_t arena_bytes, int32_t max_instances, int32_t max_tiles,
                             int32_t graph_steps, void* hip_stream, lbm_batch** out);

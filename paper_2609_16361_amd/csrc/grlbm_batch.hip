@@ -464,12 +464,14 @@ lbm_status lbm_batch_create(size_t arena_bytes, int32_t max_instances, int32_t m
       hipStreamSynchronize(b->stream) != hipSuccess)
     return bail(fail(LBM_EDEVICE, "batch table initialisation failed"));
   b->graph_steps = graph_steps;
-  // one 256-cell tile per block with plain loads and stores: the fastest shape on
-  // a mixed FP32/FP16 serving load (persistent grids trail it by 6-9%, the
-  // nontemporal hint by 5%); lbm_batch_autotune picks per workload
+  // one 256-cell tile per block with plain loads and stores, at most 2 blocks per
+  // CU: the fastest shape on a mixed FP32/FP16 serving load (persistent grids
+  // trail it by 6-9%, the nontemporal hint by 5%; uncapped blocks by 1-2% in
+  // solves/s, 4.5% on the 64 requests resident at once); lbm_batch_autotune picks
+  // per workload
   b->tune.block = 256;
   b->tune.nontemporal = 0;
-  b->tune.blocks_per_cu = 0;
+  b->tune.blocks_per_cu = 2;
   b->tune.grid = 0;
   *out = b;
   return LBM_OK;

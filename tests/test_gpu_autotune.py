@@ -54,7 +54,7 @@ def test_default_launch_shapes():
     with binding.Solver(case.params, storage=binding.LBM_STORE_F16) as s:
         assert s.launch() == dict(block=256, nontemporal=1, blocks_per_cu=0, odd_lds=1)
     with binding.Batch(1 << 24) as b:
-        assert b.info()["tuning"] == dict(block=256, nontemporal=0, blocks_per_cu=0, grid=0)
+        assert b.info()["tuning"] == dict(block=256, nontemporal=0, blocks_per_cu=2, grid=0)
 
 
 def test_autotune_before_init_is_an_error():

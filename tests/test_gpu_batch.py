@@ -52,12 +52,17 @@ SHAPES = [(1, None), (16, None), (16, (512, 1, 0, 0)), (16, (128, 0, 0, 0)), (1,
 
 @pytest.mark.parametrize("graph_steps,shape", SHAPES)
 def test_batch_equals_single_contexts_bitwise(graph_steps, shape):
+    # the last two hold 2^20 cells or more (thousands of tiles each, beside
+    # instances of a few tiles)
     cases = mix() + [(inputs.random_smooth(48, 32, 24, seed=5, amp=0.05), None),
                      (inputs.random_smooth(40, 6, 5, seed=6, amp=0.05, collision=inputs.BGK, bc=(0, 1, 0)),
-                      binding.LBM_STORE_F16)]
-    steps = [37, 20, 41, 25, 30, 18, 12, 27]
-    admit = [0, 0, 5, 9, 9, 23, 9, 2]    # clock at which each instance joins
-    with binding.Batch(1 << 26, graph_steps=graph_steps) as b:
+                      binding.LBM_STORE_F16),
+                     (inputs.random_smooth(128, 96, 86, seed=7, amp=0.05), None),
+                     (inputs.random_smooth(96, 110, 100, seed=8, amp=0.05, bc=(1, 0, 1)), binding.LBM_STORE_F16)]
+    assert all(c.cells >= 1 << 20 for c, _ in cases[-2:]) and all(c.cells < 1 << 20 for c, _ in cases[:-2])
+    steps = [37, 20, 41, 25, 30, 18, 12, 27, 15, 22]
+    admit = [0, 0, 5, 9, 9, 23, 9, 2, 9, 0]    # clock at which each instance joins
+    with binding.Batch(1 << 29, graph_steps=graph_steps) as b:
         if shape is not None:
             b.set_tuning(*shape)
             assert b.info()["tuning"] == dict(zip(("block", "nontemporal", "blocks_per_cu", "grid"), shape))
