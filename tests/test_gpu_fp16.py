@@ -75,6 +75,58 @@ def test_fp16_vortex_100_steps():
         assert e16 <= 1e-3, (k, e16)
 
 
+def test_fp16_stochastic_rounding_is_unbiased():
+    """FP16 stores round stochastically with zero mean.  In a uniform state at rest
+    every cell computes the same post-collision value of each slot, and the dither
+    of its cell and slot rounds it to one of the two FP16 neighbours; the share of
+    cells rounded up then places the value between them.  The value itself comes
+    from the FP64 oracle stepping the state the GPU holds after its start (read
+    back, so the start's own rounding is in it).  Bar: 5 standard errors of the
+    share (sqrt(p (1 - p) / N) of the FP16 spacing) plus 1e-3 of the spacing for
+    the FP32 arithmetic.  At rest the density and energy slots come back exactly
+    as stored; the six momentum slots that carry the pressure round, each over
+    262144 cells.  A biased or non-uniform dither fails it (a first 24-bit dither
+    that took the multiply's sign into the shift turned a vortex non-finite in
+    one step)."""
+    n = 64
+    p = inputs.tgv(n=n, steps=1).params
+    Q0 = np.zeros((5, n, n, n))
+    Q0[0] = p["rho_ref"] * 1.0123457
+    Q0[4] = p["E_ref"] * 1.0234567
+    sh = shift(p)
+    with binding.Solver(p, storage=F16) as s:
+        s.init(Q0)
+        g0, st0 = s.populations()
+        s.step(1)
+        g1, st1 = s.populations()
+    assert st0 == 0 and st1 == 1
+    g0 = g0.reshape(35, -1).astype(np.float64)
+    g1 = g1.reshape(35, -1).astype(np.float64)
+    N = g1.shape[1]
+    assert np.all(g0 == g0[:, :1])          # the start is uniform as well
+    one = dict(p, nx=1, ny=1, nz=1)         # one periodic cell holds the uniform state
+    f, _ = oracle.run(one, g0[:, :1] + sh[:, None], 1)
+    exact = f[:, 0] - sh
+    rounded = 0
+    for i in range(35):
+        vals = np.unique(g1[i])
+        assert len(vals) <= 2, (i, vals)
+        if len(vals) == 1:
+            # exactly representable (zero, for instance): no rounding at all
+            scale = np.abs(exact[7 * (i // 7):7 * (i // 7) + 7]).max()
+            assert abs(vals[0] - exact[i]) <= 1e-6 * scale, (i, vals, exact[i])
+            continue
+        a, b = vals
+        assert a < exact[i] < b, (i, a, exact[i], b)
+        share = np.mean(g1[i] == b)
+        est = a + share * (b - a)
+        tol = (5.0 * np.sqrt(max(share * (1 - share), 1e-12) / N) + 1e-3) * (b - a)
+        say(f"   slot {i}: exact at {(exact[i] - a) / (b - a):.4f} of the spacing, rounded up {share:.4f}")
+        assert abs(est - exact[i]) <= tol, (i, est, exact[i], tol)
+        rounded += 1
+    assert rounded >= 6
+
+
 def test_fp16_checkpoint_roundtrip():
     case = inputs.random_smooth(20, 6, 5, seed=3, amp=0.06, bc=(1, 0, 0))
     with binding.Solver(case.params, storage=F16) as s:

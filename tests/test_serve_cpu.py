@@ -201,6 +201,44 @@ def test_overdue_reservation_backfills_short_requests():
     assert o[9].admitted >= o[1].admitted
 
 
+class NoRun(RuntimeError):
+    status = -2   # LBM_ENOMEM: the byte count fits but no free run of that size does
+
+
+class FakeFragmentedBatch(FakeBatch):
+    """Refuses (LBM_ENOMEM) to add an instance with `cells` cells while more than
+    `keep` instances are resident, as an arena too fragmented for it would."""
+
+    def __init__(self, clock, cells, keep):
+        super().__init__(clock)
+        self.big, self.keep = cells, keep
+
+    def add(self, params, Q, steps, storage=0):
+        if params["nx"] * params["ny"] * params["nz"] == self.big and len(self.inst) > self.keep:
+            raise NoRun("no free run")
+        return super().add(params, Q, steps, storage)
+
+
+def test_overdue_request_waits_out_fragmentation():
+    """An overdue request whose bytes fit but for which the arena has no free run
+    holds a reservation up to the next retirement, with nothing left beside it:
+    a later short request still runs meanwhile, a later long one waits, and the
+    overdue request starts as soon as the running instances leave room."""
+    clk = FakeClock()
+    fb = FakeFragmentedBatch(clk, cells=3200, keep=0)
+    M = make_req(0, 0.0, 320, 60)                     # running, 6 chunks
+    B = make_req(1, 0.001, 3200, 20)                  # fits by bytes, not by run
+    S = make_req(2, 0.02, 320, 10)                    # one chunk
+    L = make_req(3, 0.02, 320, 500)                   # long
+    st = serve.Server(fb, arena_bytes=1 << 30, chunk_steps=10, clock=clk, order="largest",
+                      max_wait_s=0.005).serve([M, B, S, L])
+    o = {x.rid: x for x in st.outcomes}
+    assert all(x.ok for x in o.values())
+    assert o[2].completed <= o[1].admitted                      # the short one backfilled
+    assert o[3].admitted >= o[1].admitted                       # the long one waited
+    assert o[1].admitted == pytest.approx(o[0].completed)       # B at M's retirement
+
+
 def test_unknown_order_rejected():
     with pytest.raises(ValueError):
         serve.Server(FakeBatch(FakeClock()), arena_bytes=1, order="random")
