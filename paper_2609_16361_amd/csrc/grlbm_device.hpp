@@ -216,7 +216,9 @@ __device__ __forceinline__ uint32_t cell_key(int64_t cell, uint32_t skey) { retu
 // equally often (exactly uniform).  The 24-bit multiply runs at full rate, where a
 // 32-bit one is a quarter-rate instruction; it is written as the instruction
 // because in C the compiler sees that the kept bits do not depend on the factors'
-// top 8 bits, drops the 24-bit masks and emits the 32-bit multiply.
+// top 8 bits, drops the 24-bit masks and emits the 32-bit multiply.  The
+// multiplier goes in a scalar register, so `slot` must be the same in every lane
+// (every caller passes a constant of an unrolled loop).
 __device__ __forceinline__ uint32_t dither13(uint32_t hc, int slot) {
   const uint32_t m = ((0x9e3779u + 2u * (uint32_t)slot * 0x6c8e9du) & 0xffffffu) | 1u;
   uint32_t p;
