@@ -126,7 +126,7 @@ class Server:
                  chunk_steps: int = 50, result_handler=None, clock=time.perf_counter,
                  sync=None, max_instances: int = 4096, storage_override: int | None = None,
                  order: str = "largest", max_wait_s: float | None = 2.0, stop_diverged: bool = True,
-                 check_steps: int = 200, failure_handler=None, fp16_kinds=None):
+                 check_steps: int = 200, failure_handler=None, fp16_kinds=None, fp16_max_steps=None):
         self.b = backend
         self.arena_bytes = int(arena_bytes)
         self.max_cells = max_active_cells
@@ -140,6 +140,9 @@ class Server:
         # None: FP16 wherever requested; else a request of a kind outside this set
         # runs in FP32 (kinds whose stated accuracy FP16 storage does not reach)
         self.fp16_kinds = None if fp16_kinds is None else set(fp16_kinds)
+        # None: any length; else a request of more steps runs in FP32 (stochastic
+        # rounding's error grows about as the square root of the step count)
+        self.fp16_max_steps = fp16_max_steps
         # "fifo": admit arrived requests in arrival order, the first that does not
         # fit blocks the rest; "largest": among the arrived requests, largest work
         # (cells x steps) first, skipping those that do not fit yet, except that
@@ -167,6 +170,8 @@ class Server:
         if self.storage_override is not None:
             return self.storage_override
         if r.storage and self.fp16_kinds is not None and r.kind not in self.fp16_kinds:
+            return 0
+        if r.storage and self.fp16_max_steps is not None and r.steps > self.fp16_max_steps:
             return 0
         return r.storage
 

@@ -463,3 +463,15 @@ def test_fp16_only_for_the_allowed_kinds():
     st = srv.serve(reqs)
     assert sorted(seen) == [(10, 1), (20, 0), (30, 0)]
     assert [o.storage for o in st.outcomes] == [1, 0, 0]
+
+
+def test_fp16_only_up_to_a_step_count():
+    """With fp16_max_steps a request asking for FP16 storage runs in it only up to
+    that many steps; longer ones run in FP32."""
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    reqs = [make_req(0, 0.0, 320, 10, storage=1), make_req(1, 0.0, 320, 40, storage=1),
+            make_req(2, 0.0, 320, 20, storage=1)]
+    srv = serve.Server(fb, arena_bytes=1 << 30, chunk_steps=10, clock=clk, order="fifo", fp16_max_steps=20)
+    st = srv.serve(reqs)
+    assert [o.storage for o in st.outcomes] == [1, 0, 1]
