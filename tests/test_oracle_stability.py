@@ -17,7 +17,7 @@ spectrum at those speeds, 1 - omega (the transverse first moments) and 0 (the
 second moments the regularization discards).  test_regularized_linearisation_
 closed_form checks the oracle's linearisation against that union.
 
-Consequences (DESIGN notes, time-step reading):
+Consequences for the reading of the time step:
   * the regularized update is stable for advection speeds up to a_crit(omega), with
     a_crit(1) = 1/2 exactly and a_crit ~ 0.41 sqrt(2 - omega) as omega -> 2
   * the Sod point of Table 1 (omega 1.4, fastest characteristic 0.35 cells per step)
