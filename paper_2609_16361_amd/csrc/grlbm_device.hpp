@@ -166,6 +166,16 @@ __device__ __forceinline__ float ld(const T* p) {
   }
 }
 
+// The stored value itself, unconverted.
+template <typename T, bool NT>
+__device__ __forceinline__ T ldraw(const T* p) {
+  if constexpr (NT) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    return *p;
+  }
+}
+
 // A stored population is the FP32 result rounded to the storage type.  For FP16
 // the empty asm pins v as an FP32 register value first: otherwise the compiler may
 // fold the last multiply-add into the conversion (one rounding straight to FP16)
@@ -686,15 +696,42 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
   float* s2 = xs + 5 * B;      // slot 2
   float* sink = xs + 10 * B;   // [field][B], written and never read
   float f[kPop];
+  T raw[kPop];  // FP16: the rest, y and z slots as loaded, converted after the barrier
   if (act) {
+    if constexpr (sizeof(T) == 2) {
+      // FP16: the ten x slots first, so that their LDS writes, and with them the
+      // barrier, wait for those loads only while the other 25 are in flight (the
+      // odd step took 422.8 against 427.2 us at 256^3, two alternating runs).  In
+      // FP32 the same order ran 4.5% slower, so FP32 keeps the per-field order.
+      float x1[kFields], x2[kFields];
 #pragma unroll
-    for (int k = 0; k < kFields; ++k) {
-      const T* Fk = F + (int64_t)(7 * k) * S;
-      s1[k * B + lane] = ld<T, NT>(at(Fk + 1 * S, b.n));
-      s2[k * B + lane] = ld<T, NT>(at(Fk + 2 * S, b.n));
-      f[7 * k + 0] = ld<T, NT>(at(Fk, b.n));
+      for (int k = 0; k < kFields; ++k) {
+        const T* Fk = F + (int64_t)(7 * k) * S;
+        x1[k] = ld<T, NT>(at(Fk + 1 * S, b.n));
+        x2[k] = ld<T, NT>(at(Fk + 2 * S, b.n));
+      }
 #pragma unroll
-      for (int i = 3; i < kQ; ++i) f[7 * k + i] = ld<T, NT>(odd_at<ZG>(Fk, S, b, i));
+      for (int k = 0; k < kFields; ++k) {
+        const T* Fk = F + (int64_t)(7 * k) * S;
+        raw[7 * k + 0] = ldraw<T, NT>(at(Fk, b.n));
+#pragma unroll
+        for (int i = 3; i < kQ; ++i) raw[7 * k + i] = ldraw<T, NT>(odd_at<ZG>(Fk, S, b, i));
+      }
+#pragma unroll
+      for (int k = 0; k < kFields; ++k) {
+        s1[k * B + lane] = x1[k];
+        s2[k * B + lane] = x2[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kFields; ++k) {
+        const T* Fk = F + (int64_t)(7 * k) * S;
+        s1[k * B + lane] = ld<T, NT>(at(Fk + 1 * S, b.n));
+        s2[k * B + lane] = ld<T, NT>(at(Fk + 2 * S, b.n));
+        f[7 * k + 0] = ld<T, NT>(at(Fk, b.n));
+#pragma unroll
+        for (int i = 3; i < kQ; ++i) f[7 * k + i] = ld<T, NT>(odd_at<ZG>(Fk, S, b, i));
+      }
     }
   }
   const bool lo = ZG && b.lo_x;
@@ -731,6 +768,16 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
       const float v2 = r2[k * B];
       f[7 * k + 1] = in1 ? v1 : d1[k];
       f[7 * k + 2] = in2 ? v2 : d2[k];
+      if constexpr (sizeof(T) == 2) {
+        // the empty asm keeps the conversions, and the waits for these loads,
+        // after the barrier (the compiler would otherwise hoist them before it)
+        asm volatile("" : "+v"(raw[7 * k + 0]));
+#pragma unroll
+        for (int i = 3; i < kQ; ++i) asm volatile("" : "+v"(raw[7 * k + i]));
+        f[7 * k + 0] = static_cast<float>(raw[7 * k + 0]);
+#pragma unroll
+        for (int i = 3; i < kQ; ++i) f[7 * k + i] = static_cast<float>(raw[7 * k + i]);
+      }
     }
     CellDiag d;
     collide<COLL, DIAG, sizeof(T) == 2>(f, c, &d);
