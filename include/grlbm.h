@@ -345,8 +345,9 @@ lbm_status lbm_batch_set_tuning(lbm_batch* b, const lbm_batch_tuning* t);
  * steps each, restoring the populations and the clock after each trial (results do
  * not depend on the shape), and keep the fastest.  The candidates are blocks of
  * 128, 256, 512 and 1024 threads, each with and without nontemporal access, as
- * persistent grids of 8, 16 or 32 resident waves per CU and as one block per tile
- * (30 shapes).  best/best_us receive it and its
+ * persistent grids of 8, 16 or 32 resident waves per CU and as one block per tile,
+ * uncapped or (256- and 512-thread blocks) capped at 8 or 16 resident waves per CU
+ * (36 shapes).  best/best_us receive it and its
  * time per step; up to max_tried (shape, time) pairs go to tried/tried_us (may be
  * NULL), their number to *ntried.  Needs device memory for one copy of the used
  * arena. */

@@ -745,16 +745,21 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t trial_steps, lbm_batch_tunin
         cands.push_back(t);
       }
     }
-  // one block per tile, occupancy set by the registers alone
+  // one block per tile, occupancy set by the registers alone, and for 256- and
+  // 512-thread blocks capped at 8 or 16 waves per CU as well (the default shape
+  // is one of these; nontemporal access with 4 blocks of 256 per CU runs large
+  // cubes at the single-context rate)
   for (int block : {128, 256, 512, 1024})
-    for (int nt : {0, 1}) {
-      lbm_batch_tuning t{};
-      t.block = block;
-      t.nontemporal = nt;
-      t.blocks_per_cu = 0;
-      t.grid = 0;
-      cands.push_back(t);
-    }
+    for (int bpc : {0, 2, 4})
+      for (int nt : {0, 1}) {
+        if (bpc > 0 && (block < 256 || block > 512 || bpc * (block / 64) > 16)) continue;
+        lbm_batch_tuning t{};
+        t.block = block;
+        t.nontemporal = nt;
+        t.blocks_per_cu = bpc;
+        t.grid = 0;
+        cands.push_back(t);
+      }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   lbm_status st = LBM_OK;
   float best_time = 1e30f;
