@@ -73,6 +73,8 @@ TINY = [
     ("70x3x2 zero-gradient x, ragged", (70, 3, 2), (1, 0, 0)),
     ("2x2x2 zero-gradient all", (2, 2, 2), (1, 1, 1)),
     ("9x1x1 periodic thin", (9, 1, 1), (0, 0, 0)),
+    ("1x1x1 periodic, one cell its own neighbour on every axis", (1, 1, 1), (0, 0, 0)),
+    ("1x4x3 periodic, one-cell rows", (1, 4, 3), (0, 0, 0)),
 ]
 
 
