@@ -93,6 +93,25 @@ def test_batch_equals_single_contexts_bitwise(graph_steps, shape):
                 assert np.array_equal(s.moments(), Qb)
 
 
+def test_batch_degenerate_instances_bitwise():
+    """A single periodic cell (its own neighbour on every axis) and one-cell rows
+    beside an ordinary instance, in FP32 and FP16: each ends bitwise where it ends
+    alone."""
+    cases = [(inputs.random_smooth(1, 1, 1, seed=11, amp=0.05), None),
+             (inputs.random_smooth(1, 4, 3, seed=12, amp=0.05), binding.LBM_STORE_F16),
+             (inputs.random_smooth(1, 5, 2, seed=13, amp=0.05, bc=(0, 1, 1)), None),
+             (inputs.random_smooth(24, 6, 5, seed=14, amp=0.05), None)]
+    steps = [9, 14, 11, 7]
+    with binding.Batch(1 << 26, graph_steps=4) as b:
+        ids = [b.add(c.params, c.Q0, n, storage=stg) for (c, stg), n in zip(cases, steps)]
+        b.run(max(steps) + 2)
+        for k, ((c, stg), n) in enumerate(zip(cases, steps)):
+            fb, st = b.populations(ids[k])
+            assert st == n
+            say(f"compare degenerate instance {k} {c.shape}")
+            assert np.array_equal(alone(c, n, storage=stg), fb), k
+
+
 def test_batch_autotune_keeps_state():
     cases = mix()[:4]
     with binding.Batch(1 << 26, graph_steps=8) as b:

@@ -30,7 +30,7 @@ def shift(params):
 
 
 @pytest.mark.parametrize("dims,bc", [((4, 4, 4), (0, 0, 0)), ((70, 3, 2), (1, 0, 0)),
-                                     ((6, 2, 3), (1, 1, 1))])
+                                     ((6, 2, 3), (1, 1, 1)), ((1, 1, 1), (0, 0, 0))])
 def test_fp16_tiny_grids(dims, bc):
     case = inputs.random_smooth(*dims, seed=sum(dims), amp=0.08, mach=1.2, bc=bc, J_min=1e-3,
                                 sensor_gain=20.0, omega_min=1.0)
