@@ -185,10 +185,13 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
  * (default on), and an occupancy cap of `blocks_per_cu` resident blocks per compute
  * unit (1..32, enforced by reserving LDS; 0 = no cap; default 4 for FP32 storage and
  * no cap for FP16).  With `odd_lds` = 1 (the default) the odd AA step
- * moves the +-x populations through LDS so that all its HBM accesses are aligned;
- * it runs one block per x-row when nx <= 1024 and nx is a multiple of 32 (64 for
- * FP16), and otherwise tiles of 512 consecutive cells (256 for FP16); `block` and
- * `blocks_per_cu` then apply to the even step only.  With FP16 storage on grids of
+ * moves the +-x populations through LDS so that all its HBM accesses are aligned.
+ * It runs blocks of two or more whole x-rows where they fill at most 512 lanes
+ * exactly (nx not a multiple of 64, rows unpadded; FP16 two rows only), else one
+ * block per x-row when nx <= 1024 and nx is a multiple of 32 (64 for FP16), else
+ * tiles of 512 consecutive cells (256 for FP16).  Where a row is not a whole
+ * number of 128-byte lines it loads the y slots without the nontemporal hint.
+ * `block` and `blocks_per_cu` then apply to the even step only.  With FP16 storage on grids of
  * 2^23 cells and more, a lane takes two consecutive cells (4-byte accesses) in the
  * even step when `block` <= 256 and the cell count is even, and in the LDS odd step
  * when nx is 384 or 512.

@@ -61,6 +61,7 @@ constexpr int64_t kLdsPerCU = 160 * 1024;  // LDS of one gfx950 compute unit
 constexpr int kOddTileF32 = 512;           // cells per linear tile of k_step_odd_tiles, FP32
 constexpr int kOddTileF16 = 256;           // the same for FP16 storage
 constexpr int kMaxRowTile = 1024;          // longest x-row k_step_odd_tiles maps to one block
+constexpr int kMaxGroupTile = 512;         // most cells in a k_step_odd_tiles block of whole rows
 constexpr int64_t kPairMinCells = 1 << 23;  // FP16 even steps take two cells per lane from here on
 // rows map to blocks only when nx is a multiple of this (FP32 / FP16): a partly
 // filled last wave costs more than the tile edges
@@ -75,13 +76,19 @@ constexpr int kMaxRowPairs = 512;
 
 hipError_t launch_step(const StepLaunch& L, hipStream_t s);
 int64_t step_blocks(const Grid& g, int block);
+constexpr int kOddLinear = 0;    // k_step_odd_tiles: linear tiles of kOddTileF32/F16 cells
+constexpr int kOddRow = 1;       // one block per x-row
+constexpr int kOddRowGroup = 2;  // blocks of whole x-rows
 struct OddTiles {
-  bool rows;       // one block per x-row, else linear tiles of kOddTileF32/F16 cells
+  int map;         // kOddLinear, kOddRow or kOddRowGroup
+  int tile;        // cells per tile (kOddRowGroup: R * px)
   int block;       // threads per block
   int64_t blocks;  // blocks (= diagnostic partials)
   int lds;         // dynamic LDS bytes per block
+  bool y_temporal; // rows not whole 128-byte lines: y slots loaded without the nontemporal hint
 };
 OddTiles odd_tiles(const Grid& g, bool f16);  // launch shape of k_step_odd_tiles
+int odd_group_rows(const Grid& g, bool f16);  // x-rows per kOddRowGroup block, 0 if none
 int64_t launch_blocks(const StepLaunch& L);  // blocks (= diagnostic partials) of a launch
 bool even_pairs(const StepLaunch& L);        // the even step runs k_step_even_pairs
 int64_t pair_blocks(const StepLaunch& L);    // its blocks

@@ -25,6 +25,7 @@
 
 namespace grlbm {
 
+
 // ----------------------------------------------------------------- block mapping
 struct CellPos {
   int x, y, z;
@@ -122,18 +123,21 @@ __global__ void __launch_bounds__(256) k_step_even_pairs(_Float16* __restrict__ 
 }
 
 // Odd AA step over tiles of consecutive cells with the +-x populations shifted in
-// LDS (tile_update_odd): every HBM access of the x slots is aligned.  ROWS: one
-// block per x-row (nx <= 1024, blockDim.x = nx rounded up to 64); otherwise linear
-// tiles of blockDim.x cells that may start mid-row.  Bitwise the same result as
-// k_step's odd step.
-template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool ROWS, bool SRC = false>
+// LDS (tile_update_odd): every HBM access of the x slots is aligned.  MAP selects
+// the tiles: kOddRow, one block per x-row (nx <= 1024, blockDim.x = nx rounded up to
+// 64); kOddRowGroup, `tl` consecutive cells that are whole rows (tl = R * px, R >= 1,
+// tl <= blockDim.x, the lanes past tl idle), so that every x neighbour lies in the
+// tile; kOddLinear, tiles of blockDim.x cells that may start mid-row.  YT: the y
+// slots are loaded without the nontemporal hint (tile_update_odd).  Bitwise the
+// same result as k_step's odd step.
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, int MAP, bool SRC = false, bool YT = false>
 __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid g, Coll c,
                                                           float* __restrict__ partials,
-                                                          const float* __restrict__ src, uint32_t skey) {
+                                                          const float* __restrict__ src, uint32_t skey, int tl) {
   extern __shared__ float xs[];
   int n0, x = 0, y = 0, z = 0;
   bool act;
-  if constexpr (ROWS) {
+  if constexpr (MAP == kOddRow) {
     const int row = (int)blockIdx.x;
     n0 = row * g.px;
     act = (int)threadIdx.x < g.nx;
@@ -141,9 +145,9 @@ __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid
     y = row - z * g.ny;
     if (act) x = (int)threadIdx.x;
   } else {
-    n0 = (int)blockIdx.x * (int)blockDim.x;
+    n0 = (int)blockIdx.x * (MAP == kOddRowGroup ? tl : (int)blockDim.x);
     const int n = n0 + (int)threadIdx.x;
-    act = n < g.px * g.ny * g.nz;
+    act = n < g.px * g.ny * g.nz && (MAP != kOddRowGroup || (int)threadIdx.x < tl);
     if (act) {
       const int row = n / g.px;
       x = n - row * g.px;
@@ -157,7 +161,8 @@ __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid
 #pragma unroll
     for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
   }
-  tile_update_odd<COLL, T, ZG, DIAG, NT, !ROWS, SRC>(F, g, c, n0, act, x, y, z, xs, vals, skey, src);
+  tile_update_odd<COLL, T, ZG, DIAG, NT, MAP == kOddLinear, SRC, YT>(F, g, c, n0, act, x, y, z, xs, vals, skey,
+                                                                     src);
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
 
@@ -419,6 +424,22 @@ __global__ void __launch_bounds__(256) k_copy(const v4f* __restrict__ a, v4f* __
 // `lds` bytes of dynamic LDS are reserved per block (and never touched): with 160 KB
 // of LDS per CU this caps the resident blocks per CU, which the 35-stream access
 // pattern prefers low (about 16 waves per CU).
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC, bool YT>
+static hipError_t launch_odd_tiles(const StepLaunch& L, const OddTiles& ot, hipStream_t s) {
+  T* F = (T*)L.F;
+  const dim3 grid((unsigned)ot.blocks), block(ot.block);
+  if (ot.map == kOddRow)
+    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddRow, SRC, YT>), grid, block, ot.lds, s, F, L.g,
+                       L.c, L.partials, L.src, L.skey, ot.tile);
+  else if (ot.map == kOddRowGroup)
+    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddRowGroup, SRC, YT>), grid, block, ot.lds, s, F,
+                       L.g, L.c, L.partials, L.src, L.skey, ot.tile);
+  else
+    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddLinear, SRC, YT>), grid, block, ot.lds, s, F,
+                       L.g, L.c, L.partials, L.src, L.skey, ot.tile);
+  return hipGetLastError();
+}
+
 template <bool ODD, int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC>
 static hipError_t launch_step_nt(const StepLaunch& L, hipStream_t s) {
   const Grid& g = L.g;
@@ -432,13 +453,10 @@ static hipError_t launch_step_nt(const StepLaunch& L, hipStream_t s) {
   }
   if (ODD && L.odd_lds) {
     const OddTiles ot = odd_tiles(g, L.f16);
-    if (ot.rows)
-      hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, true, SRC>), dim3((unsigned)ot.blocks),
-                         dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src, L.skey);
-    else
-      hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, false, SRC>), dim3((unsigned)ot.blocks),
-                         dim3(ot.block), ot.lds, s, F, g, L.c, L.partials, L.src, L.skey);
-    return hipGetLastError();
+    if constexpr (NT) {
+      if (ot.y_temporal) return launch_odd_tiles<COLL, T, ZG, DIAG, NT, SRC, true>(L, ot, s);
+    }
+    return launch_odd_tiles<COLL, T, ZG, DIAG, NT, SRC, false>(L, ot, s);
   }
   if constexpr (!ODD && sizeof(T) == 2 && !SRC) {
     if (even_pairs(L)) {
@@ -491,20 +509,49 @@ hipError_t launch_step(const StepLaunch& L, hipStream_t s) {
 
 int64_t step_blocks(const Grid& g, int block) { return (row_cells(g) + block - 1) / block; }
 
-// Launch shape of k_step_odd_tiles: one block per x-row when a row fits in a block
-// (no index division, no tile edge inside a row), else linear tiles.  The dynamic
-// LDS holds the two x slots of a tile and a sink column (15 floats per cell),
-// padded to cap the resident waves per CU where the odd step's sustained bandwidth
-// peaked in continuous-run A/B timing on MI355X: FP32 row blocks at 8 waves per CU,
-// FP32 linear tiles of 512 cells at 16; FP16 (two-byte loads keep fewer bytes in
-// flight per wave) row blocks and 256-cell tiles at 16.
+// Whole x-rows per k_step_odd_tiles block where rows of nx cells (no padding) leave
+// the last wave of a one-row block partly idle: the fewest rows R whose R * nx cells
+// fill whole waves, up to kMaxGroupTile cells (FP16: only R = 2); 0 if there is none.
+int odd_group_rows(const Grid& g, bool f16) {
+  if (g.nx % 64 == 0 || g.px != g.nx) return 0;
+  for (int r = 2; r * g.nx <= kMaxGroupTile && (r == 2 || !f16); ++r)
+    if (r * g.nx % 64 == 0) return r;
+  return 0;
+}
+
+// Launch shape of k_step_odd_tiles, from continuous-run A/B timing on MI355X (two
+// alternating runs, cubes of 48-288).  Rows that a few whole rows fill exactly
+// (odd_group_rows) take blocks of whole rows: FP32 48-160 cells +1% to +5%, FP16
+// 96-224 cells (two rows) +3.5% to +6%, against the mappings below; FP16 blocks of
+// four rows of 48 or 80 cells lost 3-14%.  Other rows of a multiple of 32 cells
+// (FP16: 64) up to 1024 take one block per row, with no index division and no tile
+// edge; the rest take linear tiles, which also beat larger blocks of whole rows (4
+// or 5 rows of 144-200 cells: FP32 -4% to +2.4%, FP16 -5% to -15%).  The dynamic
+// LDS holds the two x slots of a tile and a sink column (15 floats per cell), padded
+// to cap the resident waves per CU where the odd step's sustained bandwidth peaked:
+// FP32 row blocks at 8 waves per CU, the rest at 16 (FP16 keeps fewer bytes in
+// flight per wave).
 OddTiles odd_tiles(const Grid& g, bool f16) {
   OddTiles t;
-  t.rows = g.nx <= kMaxRowTile && g.nx % (f16 ? kRowMultipleF16 : kRowMultipleF32) == 0;
-  const int tile = f16 ? kOddTileF16 : kOddTileF32;
-  t.block = t.rows ? (g.nx + 63) / 64 * 64 : tile;
-  t.blocks = t.rows ? (int64_t)g.ny * g.nz : (row_cells(g) + tile - 1) / tile;
-  const int waves = (t.rows && !f16) ? 8 : 16;
+  const int rows = odd_group_rows(g, f16);
+  if (rows > 0) {
+    t.map = kOddRowGroup;
+    t.tile = rows * g.px;
+    t.block = t.tile;
+    t.blocks = ((int64_t)g.ny * g.nz + rows - 1) / rows;
+  } else if (g.nx <= kMaxRowTile && g.nx % (f16 ? kRowMultipleF16 : kRowMultipleF32) == 0) {
+    t.map = kOddRow;
+    t.tile = g.px;
+    t.block = (g.nx + 63) / 64 * 64;
+    t.blocks = (int64_t)g.ny * g.nz;
+  } else {
+    t.map = kOddLinear;
+    t.tile = f16 ? kOddTileF16 : kOddTileF32;
+    t.block = t.tile;
+    t.blocks = (row_cells(g) + t.tile - 1) / t.tile;
+  }
+  t.y_temporal = (int64_t)g.px * (f16 ? 2 : 4) % 128 != 0;
+  const int waves = (t.map == kOddRow && !f16) ? 8 : 16;
   const int need = 15 * (int)sizeof(float) * t.block;
   const int per_cu = waves * 64 / t.block > 1 ? waves * 64 / t.block : 1;
   int lds = (int)(kLdsPerCU / (per_cu + 1)) + 256;

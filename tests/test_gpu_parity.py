@@ -242,18 +242,36 @@ ODD_LDS_CASES = [
     ("257x3x2 zero-gradient x, FP16 BGK", (257, 3, 2), (1, 0, 0), inputs.BGK, binding.LBM_STORE_F16),
     ("1500x2x2 zero-gradient x, linear tiles", (1500, 2, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
     ("1100x3x1 periodic FP16, linear tiles", (1100, 3, 1), (0, 0, 0), inputs.RLB_SENSOR, binding.LBM_STORE_F16),
-    ("160x3x2 zero-gradient x, one block per row", (160, 3, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
+    ("160x3x2 zero-gradient x, two whole rows per block", (160, 3, 2), (1, 0, 0), inputs.RLB_SENSOR, None),
+    ("288x3x2 zero-gradient x, one block per row, half a wave idle", (288, 3, 2), (1, 0, 0), inputs.RLB_SENSOR,
+     None),
+    ("48x5x3 periodic, four whole rows per block, ragged last block", (48, 5, 3), (0, 0, 0), inputs.RLB_SENSOR,
+     None),
     ("128x2x3 periodic FP16, one block per row", (128, 2, 3), (0, 0, 0), inputs.RLB_SENSOR, binding.LBM_STORE_F16),
     ("17x9x5 periodic, many rows per tile", (17, 9, 5), (0, 0, 0), inputs.RLB_SENSOR, None),
+    ("144x5x3 periodic, linear tiles, rows half a line off", (144, 5, 3), (0, 0, 0), inputs.RLB_SENSOR, None),
+    ("250x4x3 zero-gradient x, padded rows, linear tiles", (250, 4, 3), (1, 0, 0), inputs.RLB_SENSOR, None),
+    ("96x5x3 zero-gradient all FP16 BGK, two whole rows per block", (96, 5, 3), (1, 1, 1), inputs.BGK,
+     binding.LBM_STORE_F16),
+    ("176x3x3 periodic FP16, linear tiles, rows part of a line off", (176, 3, 3), (0, 0, 0), inputs.RLB_SENSOR,
+     binding.LBM_STORE_F16),
+    ("80x3x5 zero-gradient all FP16, linear tiles", (80, 3, 5), (1, 1, 1), inputs.RLB_SENSOR,
+     binding.LBM_STORE_F16),
+    ("160x4x3 periodic FP16, two whole rows per block", (160, 4, 3), (0, 0, 0), inputs.RLB_SENSOR,
+     binding.LBM_STORE_F16),
 ]
 
 
 @pytest.mark.parametrize("name,dims,bc,coll,storage", ODD_LDS_CASES)
 def test_odd_lds_tiles_bitwise(name, dims, bc, coll, storage):
     """The odd step over tiles of consecutive cells with the +-x populations moved
-    through LDS (one block per row when nx <= 1024 is a multiple of 32, 64 for FP16;
-    linear tiles of 512 cells, 256 for FP16, otherwise) ends bitwise where the
-    direct odd step ends, diagnostics included."""
+    through LDS ends bitwise where the direct odd step ends, diagnostics included,
+    in each of its mappings: blocks of whole rows where two or more unpadded rows
+    (nx not a multiple of 64; FP16 two rows only) fill at most 512 lanes exactly;
+    otherwise one block per row
+    when nx <= 1024 is a multiple of 32 (64 for FP16); otherwise linear tiles of 512
+    cells (256 for FP16).  Rows that are not whole 128-byte lines (most of these
+    grids) load their y slots without the nontemporal hint."""
     case = inputs.random_smooth(*dims, seed=sum(dims), amp=0.06, bc=bc, collision=coll)
     say(f"odd step via LDS {name}")
     out = []
