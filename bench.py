@@ -594,7 +594,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None if args.fp16 else measured_traffic(),
+                     "traffic": None if args.fp16 or args.n != 256 else measured_traffic(),
                      "traffic_unit": "bytes per launch",
                      "bytes_per_lup": bytes_per_lup, "avg_launch_ms": round(avg_launch_ms, 5)},
         "host_wall_s": round(t_host, 3),
