@@ -274,7 +274,8 @@ typedef struct lbm_batch lbm_batch; /* opaque */
 
 typedef struct {
   int32_t block;          /* threads per block = cells per tile (64..1024)         */
-  int32_t nontemporal;    /* nontemporal loads and stores                          */
+  int32_t nontemporal;    /* nontemporal loads and stores (the odd step still loads
+                             its y and z slots without the hint)                  */
   int32_t blocks_per_cu;  /* occupancy cap enforced by an LDS reservation (0 = off) */
   int32_t grid;           /* blocks that loop over the tiles (persistent), or 0 for
                              one block per tile                                     */

@@ -96,8 +96,13 @@ __global__ void __launch_bounds__(1024) k_batch_step(T* __restrict__ arena, cons
     const bool odd = ((t - ts) & 1) != 0;
     const uint32_t skey = step_key(t - ts);  // the instance's own step index
     if (odd) {
-      // every lane takes part (barriers inside)
-      tile_update_odd<COLL, T, true, false, NT>(F, g, c, n0, act, x, y, z, xs, nullptr, skey);
+      // every lane takes part (barriers inside).  With the nontemporal hint, the y
+      // and z slots are loaded without it: on the batch of 64 Becker tubes (4 x 4
+      // cells across, so rows and planes are fractions of a line) 62.35 against
+      // 58.09 solves/s at the fastest launch shape, 62.00 with the y slots alone;
+      // dropping it on the y and z stores as well gained nothing.
+      tile_update_odd<COLL, T, true, false, NT, true, false, NT ? 2 : 0>(F, g, c, n0, act, x, y, z, xs, nullptr,
+                                                                         skey);
     } else if (act) {
       cell_update<false, COLL, T, true, false, NT>(F, g, c, x, y, z, nullptr, skey);
     }

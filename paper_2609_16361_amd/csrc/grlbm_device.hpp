@@ -682,14 +682,16 @@ __device__ __forceinline__ void pair_update_even(_Float16* __restrict__ F, const
 // room for 15 * B floats: the two slots and a per-lane column that absorbs the LDS
 // writes a cell does not make, so that no LDS access needs a branch.  EDGES =
 // false asserts that the tile holds whole x-rows (then every x location is in the
-// tile and the edge handling compiles away).  YT loads the y slots without the
-// nontemporal hint: where rows are not whole 128-byte lines, a wave's y neighbours
-// start part of a line off, and the adjacent wave reads the rest of that line; the
-// hinted loads ran 10-12% slower there (FP32 100^3-176^3; FP16 5-9%), while the
-// stores, the z slots and aligned rows gained nothing from dropping it.  The
-// collision is the same call as in cell_update, so the results are bitwise those of
-// cell_update<true, ...>.
-template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool EDGES = true, bool SRC = false, bool YT = false>
+// tile and the edge handling compiles away).  HF > 0 loads the y slots without the
+// nontemporal hint, HF = 2 the z slots as well.  Where rows are not whole 128-byte
+// lines, a wave's y neighbours start part of a line off, and the adjacent wave
+// reads the rest of that line: the hinted loads ran 10-12% slower there (FP32
+// 100^3-176^3; FP16 5-9%), while the stores, the z slots of single grids and
+// aligned rows gained nothing from dropping it.  Batches of tubes a few cells
+// across, whose planes are a fraction of a line, gained from the z slots as well.
+// The collision is the same call as in cell_update, so the results are bitwise
+// those of cell_update<true, ...>.
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool EDGES = true, bool SRC = false, int HF = 0>
 __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g, const Coll& c, int n0,
                                                 bool act, int x, int y, int z, float* xs, float* vals,
                                                 uint32_t skey, const float* __restrict__ src = nullptr) {
@@ -719,11 +721,11 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
       for (int k = 0; k < kFields; ++k) {
         const T* Fk = F + (int64_t)(7 * k) * S;
         raw[7 * k + 0] = ldraw<T, NT>(at(Fk, b.n));
-        if constexpr (YT) {
+        if constexpr (HF > 0) {
           raw[7 * k + 3] = ldraw<T, false>(odd_at<ZG>(Fk, S, b, 3));
           raw[7 * k + 4] = ldraw<T, false>(odd_at<ZG>(Fk, S, b, 4));
-          raw[7 * k + 5] = ldraw<T, NT>(odd_at<ZG>(Fk, S, b, 5));
-          raw[7 * k + 6] = ldraw<T, NT>(odd_at<ZG>(Fk, S, b, 6));
+          raw[7 * k + 5] = ldraw<T, NT && HF < 2>(odd_at<ZG>(Fk, S, b, 5));
+          raw[7 * k + 6] = ldraw<T, NT && HF < 2>(odd_at<ZG>(Fk, S, b, 6));
         } else {
 #pragma unroll
           for (int i = 3; i < kQ; ++i) raw[7 * k + i] = ldraw<T, NT>(odd_at<ZG>(Fk, S, b, i));
@@ -741,11 +743,11 @@ __device__ __forceinline__ void tile_update_odd(T* __restrict__ F, const Grid& g
         s1[k * B + lane] = ld<T, NT>(at(Fk + 1 * S, b.n));
         s2[k * B + lane] = ld<T, NT>(at(Fk + 2 * S, b.n));
         f[7 * k + 0] = ld<T, NT>(at(Fk, b.n));
-        if constexpr (YT) {
+        if constexpr (HF > 0) {
           f[7 * k + 3] = ld<T, false>(odd_at<ZG>(Fk, S, b, 3));
           f[7 * k + 4] = ld<T, false>(odd_at<ZG>(Fk, S, b, 4));
-          f[7 * k + 5] = ld<T, NT>(odd_at<ZG>(Fk, S, b, 5));
-          f[7 * k + 6] = ld<T, NT>(odd_at<ZG>(Fk, S, b, 6));
+          f[7 * k + 5] = ld<T, NT && HF < 2>(odd_at<ZG>(Fk, S, b, 5));
+          f[7 * k + 6] = ld<T, NT && HF < 2>(odd_at<ZG>(Fk, S, b, 6));
         } else {
 #pragma unroll
           for (int i = 3; i < kQ; ++i) f[7 * k + i] = ld<T, NT>(odd_at<ZG>(Fk, S, b, i));

@@ -127,10 +127,10 @@ __global__ void __launch_bounds__(256) k_step_even_pairs(_Float16* __restrict__ 
 // the tiles: kOddRow, one block per x-row (nx <= 1024, blockDim.x = nx rounded up to
 // 64); kOddRowGroup, `tl` consecutive cells that are whole rows (tl = R * px, R >= 1,
 // tl <= blockDim.x, the lanes past tl idle), so that every x neighbour lies in the
-// tile; kOddLinear, tiles of blockDim.x cells that may start mid-row.  YT: the y
-// slots are loaded without the nontemporal hint (tile_update_odd).  Bitwise the
-// same result as k_step's odd step.
-template <int COLL, typename T, bool ZG, bool DIAG, bool NT, int MAP, bool SRC = false, bool YT = false>
+// tile; kOddLinear, tiles of blockDim.x cells that may start mid-row.  HF: the y
+// slots (HF = 1) are loaded without the nontemporal hint (tile_update_odd).
+// Bitwise the same result as k_step's odd step.
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, int MAP, bool SRC = false, int HF = 0>
 __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid g, Coll c,
                                                           float* __restrict__ partials,
                                                           const float* __restrict__ src, uint32_t skey, int tl) {
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(1024) k_step_odd_tiles(T* __restrict__ F, Grid
 #pragma unroll
     for (int j = 0; j < kDiagVals; ++j) vals[j] = 0.0f;
   }
-  tile_update_odd<COLL, T, ZG, DIAG, NT, MAP == kOddLinear, SRC, YT>(F, g, c, n0, act, x, y, z, xs, vals, skey,
+  tile_update_odd<COLL, T, ZG, DIAG, NT, MAP == kOddLinear, SRC, HF>(F, g, c, n0, act, x, y, z, xs, vals, skey,
                                                                      src);
   if constexpr (DIAG) block_reduce_store(vals, partials);
 }
@@ -424,18 +424,18 @@ __global__ void __launch_bounds__(256) k_copy(const v4f* __restrict__ a, v4f* __
 // `lds` bytes of dynamic LDS are reserved per block (and never touched): with 160 KB
 // of LDS per CU this caps the resident blocks per CU, which the 35-stream access
 // pattern prefers low (about 16 waves per CU).
-template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC, bool YT>
+template <int COLL, typename T, bool ZG, bool DIAG, bool NT, bool SRC, int HF>
 static hipError_t launch_odd_tiles(const StepLaunch& L, const OddTiles& ot, hipStream_t s) {
   T* F = (T*)L.F;
   const dim3 grid((unsigned)ot.blocks), block(ot.block);
   if (ot.map == kOddRow)
-    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddRow, SRC, YT>), grid, block, ot.lds, s, F, L.g,
+    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddRow, SRC, HF>), grid, block, ot.lds, s, F, L.g,
                        L.c, L.partials, L.src, L.skey, ot.tile);
   else if (ot.map == kOddRowGroup)
-    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddRowGroup, SRC, YT>), grid, block, ot.lds, s, F,
+    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddRowGroup, SRC, HF>), grid, block, ot.lds, s, F,
                        L.g, L.c, L.partials, L.src, L.skey, ot.tile);
   else
-    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddLinear, SRC, YT>), grid, block, ot.lds, s, F,
+    hipLaunchKernelGGL((k_step_odd_tiles<COLL, T, ZG, DIAG, NT, kOddLinear, SRC, HF>), grid, block, ot.lds, s, F,
                        L.g, L.c, L.partials, L.src, L.skey, ot.tile);
   return hipGetLastError();
 }
@@ -454,9 +454,9 @@ static hipError_t launch_step_nt(const StepLaunch& L, hipStream_t s) {
   if (ODD && L.odd_lds) {
     const OddTiles ot = odd_tiles(g, L.f16);
     if constexpr (NT) {
-      if (ot.y_temporal) return launch_odd_tiles<COLL, T, ZG, DIAG, NT, SRC, true>(L, ot, s);
+      if (ot.y_temporal) return launch_odd_tiles<COLL, T, ZG, DIAG, NT, SRC, 1>(L, ot, s);
     }
-    return launch_odd_tiles<COLL, T, ZG, DIAG, NT, SRC, false>(L, ot, s);
+    return launch_odd_tiles<COLL, T, ZG, DIAG, NT, SRC, 0>(L, ot, s);
   }
   if constexpr (!ODD && sizeof(T) == 2 && !SRC) {
     if (even_pairs(L)) {
