@@ -513,7 +513,7 @@ int64_t step_blocks(const Grid& g, int block) { return (row_cells(g) + block - 1
 // the last wave of a one-row block partly idle: the fewest rows R whose R * nx cells
 // fill whole waves, up to kMaxGroupTile cells (FP16: only R = 2); 0 if there is none.
 int odd_group_rows(const Grid& g, bool f16) {
-  if (g.nx % 64 == 0 || g.px != g.nx) return 0;
+  if (g.nx % 64 == 0 || g.px != g.nx || g.nx > kMaxGroupTile) return 0;
   for (int r = 2; r * g.nx <= kMaxGroupTile && (r == 2 || !f16); ++r)
     if (r * g.nx % 64 == 0) return r;
   return 0;
