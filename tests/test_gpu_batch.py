@@ -47,7 +47,7 @@ def mix():
 # tiles of 128 cells and back, so the rounded grid changes and the graph is
 # captured again on the way.
 SHAPES = [(1, None), (16, None), (16, (512, 1, 0, 0)), (16, (128, 0, 0, 0)), (1, (128, 1, 0, 0)),
-          (16, (256, 0, 4, 7))]
+          (16, (256, 0, 4, 7)), (16, (256, 1, 4, 0))]
 
 
 @pytest.mark.parametrize("graph_steps,shape", SHAPES)
