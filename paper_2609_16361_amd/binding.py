@@ -345,10 +345,11 @@ class Solver:
         self.shape = (self.cparams.nz, self.cparams.ny, self.cparams.nx)
         self.ctx = lbm_create(self.cparams, stream)
         if block is not None or nontemporal is not None or blocks_per_cu is not None or not odd_lds:
-            # unspecified settings keep the library's defaults
-            default_bpc = 0 if self.cparams.storage == LBM_STORE_F16 else 4
-            lbm_set_launch(self.ctx, block or 256, True if nontemporal is None else bool(nontemporal),
-                           default_bpc if blocks_per_cu is None else blocks_per_cu, odd_lds)
+            # unspecified settings keep the library's defaults for this grid
+            d = lbm_get_launch(self.ctx)
+            lbm_set_launch(self.ctx, d["block"] if block is None else block,
+                           d["nontemporal"] if nontemporal is None else bool(nontemporal),
+                           d["blocks_per_cu"] if blocks_per_cu is None else blocks_per_cu, odd_lds)
 
     def init(self, Q):
         lbm_init_fields(self.ctx, np.asarray(Q, dtype=np.float64).reshape((5,) + self.shape))

@@ -247,6 +247,18 @@ constexpr int kDiagVals = 9;
 constexpr int32_t kRingCap = 1024;
 constexpr int kDefaultBlocksPerCuF32 = 4;
 
+// Nontemporal access is the default except for states of kNtOffMin up to kNtOffMax
+// bytes, about the size of the 256 MB Infinity Cache, which keeps part of such a
+// state between steps unless the hint evicts it.  Measured on MI355X over cubes
+// (GLUP/s without / with the hint): FP32 64^3 (37 MB) 18.7 / 16.0, 96^3 (124 MB)
+// 23.6 / 18.7, 128^3 (294 MB) 21.1 / 20.1, but 136^3 (352 MB) 19.0 / 20.1 and 48^3
+// (15 MB) 9.9 / 10.6; FP16 72^3 (26 MB) 29.1 / 26.7, 128^3 (147 MB) 44.8 / 37.7,
+// 144^3 (209 MB) 41.2 / 35.6, 160^3 (287 MB) 37.1 / 37.3, but 192^3 (495 MB) 37.5 /
+// 39.8 and 64^3 (18 MB) 19.0 / 23.2.
+constexpr int64_t kNtOffMin = 24ll << 20;
+constexpr int64_t kNtOffMax = 320ll << 20;
+bool default_nontemporal(int64_t state_bytes) { return state_bytes < kNtOffMin || state_bytes >= kNtOffMax; }
+
 }  // namespace
 
 struct lbm_ctx {
@@ -338,6 +350,7 @@ lbm_status create_common(const lbm_params* p, void* buf, size_t bytes, void* str
   // wave) uncapped -- the fastest shapes in continuous-run A/B timing on MI355X for
   // both short (256-cell) and long (1024- and 4096-cell) rows.
   c->block = 256;
+  c->nt = default_nontemporal((int64_t)c->F_bytes);
   c->bpc = p->storage == LBM_STORE_F16 ? 0 : kDefaultBlocksPerCuF32;
   c->lds = lds_for_blocks_per_cu(c->bpc);
   auto bail = [&](lbm_status s) {
@@ -812,7 +825,7 @@ lbm_status lbm_step_noalloc(const lbm_params* p, void* F_dev, int64_t step, int6
   L.block = 256;  // the launch shape of a new context
   L.coll = p->collision;
   L.f16 = false;
-  L.nt = true;
+  L.nt = default_nontemporal((int64_t)state_bytes(p));
   L.lds = lds_for_blocks_per_cu(kDefaultBlocksPerCuF32);
   L.odd_lds = true;
   L.src = nullptr;

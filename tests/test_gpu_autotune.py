@@ -55,6 +55,17 @@ def test_default_launch_shapes():
         assert s.launch() == dict(block=256, nontemporal=1, blocks_per_cu=0, odd_lds=1)
     with binding.Batch(1 << 24) as b:
         assert b.info()["tuning"] == dict(block=256, nontemporal=0, blocks_per_cu=2, grid=0)
+    # states of 24 MB up to 320 MB default to plain access; smaller and larger ones
+    # to nontemporal access
+    F16 = binding.LBM_STORE_F16
+    for dims, stg, nt in (((96, 96, 96), None, 0), ((136, 136, 136), None, 1), ((128, 128, 128), F16, 0),
+                          ((48, 48, 48), F16, 1), ((256, 256, 256), None, 1)):
+        p = dict(case.params, nx=dims[0], ny=dims[1], nz=dims[2])
+        with binding.Solver(p, storage=stg) as s:
+            assert s.launch()["nontemporal"] == nt, (dims, stg)
+        # a partial override keeps the grid's default for the rest
+        with binding.Solver(p, storage=stg, block=512) as s:
+            assert s.launch()["nontemporal"] == nt and s.launch()["block"] == 512, (dims, stg)
 
 
 def test_autotune_before_init_is_an_error():
