@@ -312,6 +312,12 @@ FP16_KINDS = ("sod", "becker")
 # FP16 Sod tubes of the 1000-request trace reached about 8.2e-5 sqrt(steps) against
 # FP32, which passes the 1e-2 bar at about 15000 steps; longer requests run in FP32
 FP16_MAX_STEPS = 12000
+# Requests whose state takes this much or more run in contexts of their own beside
+# the batch: from about this size the single-context kernels, with plain access up
+# to 320 MB and nontemporal beyond, move a state faster than the batch kernel does
+# (the mix's vortices of 63^3-127^3 alone at 17.9-22.6 GLUP/s against 17.4 for all
+# of its vortices in one batch), while smaller states are launch-bound alone.
+SOLO_MIN_BYTES = 24 << 20
 
 
 def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9, chunk=50,
@@ -331,6 +337,8 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
            "divergence": "checked every 200 steps in every leg; a diverged request stops at once as failed",
            "rejection": "a request whose initial density or pressure is not positive is refused by the "
                         "library (LBM_EINVAL) in every leg and counted as rejected",
+           "solo": f"batched legs: requests of {SOLO_MIN_BYTES >> 20} MiB of state or more run in contexts of "
+                   "their own beside the batch, one chunk at a time",
            "offered_glup": work / 1e9,
            "mix": {k: sum(1 for r in trace if r.kind == k) for k in ("sod", "tgv", "becker")},
            "fp16_share": sum(r.storage for r in trace) / count,
@@ -395,7 +403,10 @@ def bench_serve(stream, count=64, rate=50.0, seed=1, budget_bytes=200 * 10 ** 9,
                                sync=torch.cuda.synchronize, max_active_cells=max_active_cells,
                                storage_override=storage_override, fp16_kinds=FP16_KINDS,
                                fp16_max_steps=FP16_MAX_STEPS,
-                               failure_handler=lambda req: finished(req, False))
+                               failure_handler=lambda req: finished(req, False),
+                               solo_factory=lambda req, stg: binding.Solver(req.case.params, stream=stream.cuda_stream,
+                                                                            storage=stg),
+                               solo_min_bytes=SOLO_MIN_BYTES)
             return srv.serve(trace)
 
     # storage as requested (FP16 for about half the requests), then every request in

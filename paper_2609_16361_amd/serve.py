@@ -126,8 +126,20 @@ class Server:
                  chunk_steps: int = 50, result_handler=None, clock=time.perf_counter,
                  sync=None, max_instances: int = 4096, storage_override: int | None = None,
                  order: str = "largest", max_wait_s: float | None = 2.0, stop_diverged: bool = True,
-                 check_steps: int = 200, failure_handler=None, fp16_kinds=None, fp16_max_steps=None):
+                 check_steps: int = 200, failure_handler=None, fp16_kinds=None, fp16_max_steps=None,
+                 solo_factory=None, solo_min_bytes: int | None = None):
         self.b = backend
+        # Requests whose state takes solo_min_bytes or more run in a context of their
+        # own, made by solo_factory(request, storage) (an object with init(Q),
+        # step(n, diag_every), diagnostics(), moments() and close(), on the stream
+        # the batch uses), stepped one chunk at a time after each batch chunk; the
+        # rest share the batch.  The single-context kernels move such states faster
+        # than the batch kernel does (whole-row tiles, a launch shape chosen for the
+        # grid), and the results are those of the same request run alone.
+        self.solo_factory = solo_factory
+        self.solo_min = solo_min_bytes if solo_factory is not None else None
+        self.stop_diverged = bool(stop_diverged)
+        self.check_steps = int(check_steps)
         self.arena_bytes = int(arena_bytes)
         self.max_cells = max_active_cells
         self.chunk = int(chunk_steps)
@@ -232,6 +244,7 @@ class Server:
         # hot path: comparing requests compares their arrays)
         pending = {r.rid: r for r in reqs}
         active = {}                 # instance id -> (request, bytes, steps run when admitted)
+        solos = {}                  # id ("solo", request id) -> [context, steps done]
         used_bytes = 0
         used_cells = 0
         steps_run = 0               # steps every resident instance has been offered so far
@@ -264,7 +277,17 @@ class Server:
                     continue
                 if fits:
                     try:
-                        iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=stg[r.rid])
+                        if self.solo_min is not None and nb >= self.solo_min:
+                            iid = ("solo", r.rid)
+                            ctx = self.solo_factory(r, stg[r.rid])
+                            try:
+                                ctx.init(r.case.Q0)
+                            except BaseException:
+                                ctx.close()
+                                raise
+                            solos[iid] = [ctx, 0]
+                        else:
+                            iid = self.b.add(r.case.params, r.case.Q0, r.steps, storage=stg[r.rid])
                     except RuntimeError as e:
                         status = getattr(e, "status", None)
                         if status == EINVAL:
@@ -303,13 +326,45 @@ class Server:
             # one chunk (a graph replay) for everything on the device; an instance that
             # reaches its step count inside the chunk stays frozen there
             t_start = self.clock() - t0
-            self.b.run(self.chunk)
+            if len(active) > len(solos):
+                self.b.run(self.chunk)
+            for iid, ent in solos.items():
+                k = min(self.chunk, active[iid][0].steps - ent[1])
+                if k > 0:
+                    # the sequential baseline's divergence check: a diagnostic
+                    # record on every step that is a multiple of check_steps
+                    ent[0].step(k, self.check_steps if self.stop_diverged else 0)
+                    ent[1] += k
             steps_run += self.chunk
             st.chunks += 1
             self.sync()
             tnow = self.clock() - t0
             st.timeline.append((t_start, tnow, len(active), used_cells))
-            for iid in [i for i in active if self.b.query(i)[1]]:
+            for iid in list(solos):
+                ctx, done = solos[iid]
+                r, nb, _ = active[iid]
+                diverged = False
+                if self.stop_diverged:
+                    recs, _ = ctx.diagnostics()
+                    diverged = any(rec["nonfinite"] > 0 for rec in recs)
+                if not diverged and done < r.steps:
+                    continue
+                del active[iid], solos[iid]
+                o = out[r.rid]
+                o.completed = tnow
+                if diverged:
+                    o.ok = False
+                    st.stopped += 1
+                else:
+                    res = self.handle(r, ctx.moments())
+                    o.ok = bool(res) if isinstance(res, (bool, np.bool_)) else True
+                    o.result = res
+                ctx.close()
+                used_bytes -= nb
+                used_cells -= ncells[r.rid]
+                if diverged and self.on_failure is not None:
+                    self.on_failure(r)
+            for iid in [i for i in active if i not in solos and self.b.query(i)[1]]:
                 r, nb, _ = active.pop(iid)
                 Q = self.b.moments(iid)
                 o = out[r.rid]
@@ -320,7 +375,7 @@ class Server:
                 self.b.remove(iid)
                 used_bytes -= nb
                 used_cells -= ncells[r.rid]
-            if self.check is not None and active and st.chunks % self.check_chunks == 0:
+            if self.check is not None and len(active) > len(solos) and st.chunks % self.check_chunks == 0:
                 for iid in self.check():
                     if iid not in active:
                         continue

@@ -11,8 +11,8 @@ from paper_2609_16361_amd import binding, inputs, serve
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("stop_diverged", [True, False])
-def test_results_alone_equal_in_mix(stop_diverged):
+@pytest.mark.parametrize("stop_diverged,solo_min", [(True, None), (False, None), (True, 1 << 19)])
+def test_results_alone_equal_in_mix(stop_diverged, solo_min):
     """Each result in the mix is bitwise the request's result alone.  The mix holds
     a Mach 1.5 vortex whose isothermal initial pressure is negative: the library
     refuses it (LBM_EINVAL), in the mix and alone, and the server counts it as
@@ -20,7 +20,9 @@ def test_results_alone_equal_in_mix(stop_diverged):
     which stops being finite early (by step 60 in the FP64 oracle).  With the
     divergence check that request is retired early as failed (no result); without
     it, it runs to its step count and its non-finite state is bitwise the one
-    alone."""
+    alone.  With solo_min, the requests whose state takes that many bytes or more
+    (the diverging vortex among them) run in contexts of their own beside the
+    batch, under the same checks, and their results too are bitwise those alone."""
     trace = inputs.serving_trace(count=12, rate=400.0, seed=5, steps_range=(40, 400),
                                  tgv_n=(12, 20), sod_n=(64, 300), becker_L=(64, 200))
     early = inputs.Request(100, 0.0, "tgv", inputs.tgv(n=16, mach=1.25, cfl=0.3, steps=200, diag_every=0),
@@ -32,11 +34,21 @@ def test_results_alone_equal_in_mix(stop_diverged):
         results[req.rid] = Q
         return bool(np.isfinite(Q).all())
 
+    solos = []
+
+    def solo(r, storage):
+        solos.append(r.rid)
+        return binding.Solver(r.case.params, storage=storage)
+
     with binding.Batch(1 << 28, graph_steps=16) as b:
         srv = serve.Server(b, arena_bytes=(1 << 28) - (1 << 20), chunk_steps=16,
                            result_handler=keep, sync=torch.cuda.synchronize,
-                           stop_diverged=stop_diverged, check_steps=16, failure_handler=stopped.append)
+                           stop_diverged=stop_diverged, check_steps=16, failure_handler=stopped.append,
+                           solo_factory=solo if solo_min else None, solo_min_bytes=solo_min)
         st = srv.serve(trace)
+    if solo_min:
+        big = {r.rid for r in trace if serve.state_bytes(r.case.params, r.storage) >= solo_min}
+        assert set(solos) == big and early.rid in big and 2 <= len(big) < len(trace) - 2, (solos, big)
     s = st.summary()
     print(s, flush=True)
     assert st.max_active >= 3    # requests overlapped

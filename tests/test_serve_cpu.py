@@ -475,3 +475,66 @@ def test_fp16_only_up_to_a_step_count():
     srv = serve.Server(fb, arena_bytes=1 << 30, chunk_steps=10, clock=clk, order="fifo", fp16_max_steps=20)
     st = srv.serve(reqs)
     assert [o.storage for o in st.outcomes] == [1, 0, 1]
+
+
+def test_large_requests_run_in_contexts_of_their_own():
+    """Requests whose state reaches solo_min_bytes run in contexts of their own,
+    stepped one chunk at a time beside the batch: exactly their step count, their
+    own divergence check (records on every multiple of check_steps), and
+    rejection when the library refuses the state; the rest share the batch."""
+    clk = FakeClock()
+    b = FakeBatch(clk)
+    made, closed = [], []
+
+    class Solo:
+        def __init__(self, r, storage):
+            self.r, self.n, self.recs = r, 0, []
+            self.bad_from = r.case.params.get("bad_from")
+            made.append(r.rid)
+
+        def init(self, Q):
+            if self.r.case.params.get("refuse"):
+                raise Refused("initial density not positive")
+            self.Q = Q
+
+        def step(self, n, diag_every=0):
+            for t in range(self.n, self.n + n):
+                if diag_every and t % diag_every == 0:
+                    self.recs.append({"step": t, "nonfinite": int(self.bad_from is not None and t >= self.bad_from)})
+            self.n += n
+            clk.t += n * 1e-3
+
+        def diagnostics(self):
+            r, self.recs = self.recs, []
+            return r, 0
+
+        def moments(self):
+            return self.Q + self.n
+
+        def close(self):
+            closed.append(self.r.rid)
+
+    big, small = 3200, 320
+    reqs = [make_req(0, 0.0, big, 130), make_req(1, 0.0, small, 70), make_req(2, 0.0, big, 1000),
+            make_req(3, 0.0, big, 90), make_req(4, 0.0, small, 40)]
+    reqs[2].case.params["bad_from"] = 450          # diverges after 450 steps
+    reqs[3].case.params["refuse"] = True
+    limit = serve.state_bytes(reqs[0].case.params, 0)
+    assert serve.state_bytes(reqs[1].case.params, 0) < limit
+    results, failed = {}, []
+
+    def handler(r, Q):
+        results[r.rid] = float(Q.flat[0])
+        return True
+
+    srv = serve.Server(b, arena_bytes=1 << 30, chunk_steps=50, clock=clk, result_handler=handler,
+                       check_steps=200, failure_handler=failed.append, solo_factory=Solo, solo_min_bytes=limit)
+    st = srv.serve(reqs)
+    assert sorted(made) == [0, 2, 3] and sorted(closed) == [0, 2, 3]
+    assert sorted(b.added_steps) == [40, 70]       # only the small ones share the batch
+    assert results == {0: 130.0, 1: 70.0, 4: 40.0}  # each stopped at its own step count
+    o = {x.rid: x for x in st.outcomes}
+    assert not o[2].ok and not o[2].rejected and [r.rid for r in failed] == [2]
+    assert o[3].rejected and not o[3].ok
+    s = st.summary()
+    assert (s["completed"], s["failed"], s["rejected"], s["stopped_diverged"]) == (3, 1, 1, 1)
