@@ -250,11 +250,11 @@ constexpr int kDefaultBlocksPerCuF32 = 4;
 // Nontemporal access is the default except for states of kNtOffMin up to kNtOffMax
 // bytes, about the size of the 256 MB Infinity Cache, which keeps part of such a
 // state between steps unless the hint evicts it.  Measured on MI355X over cubes
-// (GLUP/s without / with the hint): FP32 64^3 (37 MB) 18.7 / 16.0, 96^3 (124 MB)
-// 23.6 / 18.7, 128^3 (294 MB) 21.1 / 20.1, but 136^3 (352 MB) 19.0 / 20.1 and 48^3
-// (15 MB) 9.9 / 10.6; FP16 72^3 (26 MB) 29.1 / 26.7, 128^3 (147 MB) 44.8 / 37.7,
-// 144^3 (209 MB) 41.2 / 35.6, 160^3 (287 MB) 37.1 / 37.3, but 192^3 (495 MB) 37.5 /
-// 39.8 and 64^3 (18 MB) 19.0 / 23.2.
+// (GLUP/s without / with the hint, each storage's default occupancy cap): FP32 64^3
+// (37 MB) 18.7 / 16.0, 96^3 (124 MB) 23.5 / 18.2, 128^3 (294 MB) 21.1 / 20.1, but
+// 136^3 (352 MB) 19.0 / 20.1 and 48^3 (15 MB) 9.9 / 10.6; FP16 72^3 (26 MB) 29.1 /
+// 26.7, 128^3 (147 MB) 44.8 / 37.7, 144^3 (209 MB) 41.2 / 35.6, 160^3 (287 MB) 37.1
+// / 37.3, but 192^3 (495 MB) 37.1 / 39.8 and 64^3 (18 MB) 19.0 / 23.2.
 constexpr int64_t kNtOffMin = 24ll << 20;
 constexpr int64_t kNtOffMax = 320ll << 20;
 bool default_nontemporal(int64_t state_bytes) { return state_bytes < kNtOffMin || state_bytes >= kNtOffMax; }
