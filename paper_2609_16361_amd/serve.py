@@ -135,7 +135,11 @@ class Server:
         # the batch uses), stepped one chunk at a time after each batch chunk; the
         # rest share the batch.  The single-context kernels move such states faster
         # than the batch kernel does (whole-row tiles, a launch shape chosen for the
-        # grid), and the results are those of the same request run alone.
+        # grid), and the results are those of the same request run alone.  A solo
+        # state is allocated by the factory, outside the batch's arena, and counts
+        # against the same byte budget and cell cap: the device must hold the arena
+        # and the solo states together (the benchmark's cell cap of 8 Mi cells keeps
+        # them below 1.2 GB beside its 200 GB arena).
         self.solo_factory = solo_factory
         self.solo_min = solo_min_bytes if solo_factory is not None else None
         self.stop_diverged = bool(stop_diverged)
