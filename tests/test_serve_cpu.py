@@ -538,3 +538,56 @@ def test_large_requests_run_in_contexts_of_their_own():
     assert o[3].rejected and not o[3].ok
     s = st.summary()
     assert (s["completed"], s["failed"], s["rejected"], s["stopped_diverged"]) == (3, 1, 1, 1)
+
+
+class FakeSolo:
+    """A context of its own for the fake clock: a step costs `dt` fake seconds."""
+
+    def __init__(self, clk, dt=1e-3):
+        self.clk, self.dt, self.n = clk, dt, 0
+
+    def init(self, Q):
+        self.Q = Q
+
+    def step(self, n, diag_every=0):
+        self.n += n
+        self.clk.t += n * self.dt
+
+    def diagnostics(self):
+        return [], 0
+
+    def moments(self):
+        return self.Q + self.n
+
+    def close(self):
+        pass
+
+
+def test_overdue_solo_request_keeps_its_place():
+    """The reservation and backfilling hold when the overdue request, or the one
+    running ahead of it, runs in a context of its own: the large request starts
+    exactly when the request ahead of it retires, short requests fill the wait,
+    and every result is its exact step count."""
+    clk = FakeClock()
+    fb = FakeBatch(clk)
+    M = make_req(0, 0.0, 1600, 100)                                          # running, 10 chunks
+    B = make_req(1, 0.001, 3200, 20)                                         # does not fit beside M
+    S = [make_req(2 + i, 0.02 + 0.01 * i, 320, 10) for i in range(3)]       # one chunk each
+    budget = serve.state_bytes(B.case.params, 0) + serve.state_bytes(S[0].case.params, 0)
+    results = {}
+
+    def keep(r, Q):
+        results[r.rid] = float(Q.flat[0])
+        return True
+
+    solo_min = serve.state_bytes(M.case.params, 0)                           # M and B run alone
+    st = serve.Server(fb, arena_bytes=budget, chunk_steps=10, clock=clk, order="largest", max_wait_s=0.005,
+                      result_handler=keep, solo_factory=lambda r, stg: FakeSolo(clk),
+                      solo_min_bytes=solo_min).serve([M, B, *S])
+    o = {x.rid: x for x in st.outcomes}
+    assert all(x.ok for x in o.values())
+    assert sorted(fb.added_steps) == [10, 10, 10]                            # only the short ones batched
+    assert o[1].admitted == pytest.approx(o[0].completed)
+    for x in S:
+        assert o[x.rid].admitted < o[1].admitted and o[x.rid].completed <= o[1].admitted
+    assert results == {0: 100.0, 1: 20.0, 2: 10.0, 3: 10.0, 4: 10.0}
