@@ -182,7 +182,7 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* f, int64_t step);
 
 /* Launch shape of the collide-and-stream kernels: `block` threads per block (a
  * multiple of 64 in [64, 1024]; default 256), nontemporal loads/stores on or off
- * (default on, except for population states of 24 MB up to 320 MB, which the
+ * (default on, except for population states of 24 MiB up to 320 MiB, which the
  * 256 MB Infinity Cache partly keeps between steps), and an occupancy cap of `blocks_per_cu` resident blocks per compute
  * unit (1..32, enforced by reserving LDS; 0 = no cap; default 4 for FP32 storage and
  * no cap for FP16).  With `odd_lds` = 1 (the default) the odd AA step
